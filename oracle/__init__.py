@@ -1,0 +1,213 @@
+"""ctypes front-end of the FP64 CPU oracle (``ssgp_oracle.c``).
+
+TEST INFRASTRUCTURE.  The oracle is the plain, slow reference that the HIP
+path is checked against.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import it; the product package never
+does.  It shares no code with the GPU library.
+
+Every array is numpy ``complex128`` of shape ``(3, ny, nx)`` (2D) or
+``(3, nx)`` (1D), C-contiguous, component order (+1, 0, -1), x fastest.
+Functions that change a state return a new array (the input is copied).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ssgp_oracle.c")
+_LIB = os.path.join(_HERE, "libssgp_oracle.so")
+
+SO_NONE, SO_PX_SX, SO_PX_SY, SO_PX_SZ, SO_RASHBA, SO_DRESSELHAUS, SO_ERD = range(7)
+RENORM_AUTO, RENORM_NORM, RENORM_FIXED_M = range(3)
+
+OBS_NAMES = ("N+1", "N0", "N-1", "N", "M", "E", "E_kin", "E_trap", "E_c0", "E_c2",
+             "E_rabi", "E_so", "rms+1", "rms0", "rms-1", "rms")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, OpenMP over grid lines)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("c0", ctypes.c_double), ("c2", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("omega", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("dt", ctypes.c_double),
+                ("imag", ctypes.c_int), ("so", ctypes.c_int), ("renorm", ctypes.c_int),
+                ("mag0", ctypes.c_double)]
+
+
+@dataclass
+class Cfg:
+    """Grid and model parameters of one run (Table 2 of the paper)."""
+    dim: int
+    nx: int
+    ny: int = 1
+    dx: float = 0.1
+    dy: float = 0.1
+    c0: float = 0.0
+    c2: float = 0.0
+    gamma: float = 0.0
+    omega: float = 0.0
+    dt: float = 1e-3
+    imag: bool = True
+    so: int = SO_NONE
+    renorm: int = RENORM_AUTO
+    mag0: float = 0.0
+    kappa: float = 1.0
+
+    def c(self) -> _Cfg:
+        return _Cfg(self.dim, self.nx, self.ny if self.dim == 2 else 1, self.dx, self.dy,
+                    self.c0, self.c2, self.gamma, self.omega, self.kappa, self.dt,
+                    1 if self.imag else 0, self.so, self.renorm, self.mag0)
+
+    def shape(self):
+        return (3, self.ny, self.nx) if self.dim == 2 else (3, self.nx)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(_Cfg)
+        vp = ctypes.c_void_p
+        for name in ("ora_calcnu", "ora_herm", "ora_so", "ora_cn_x", "ora_cn_y",
+                     "ora_pointwise_dual_value", "ora_cn_x_adjoint", "ora_cn_y_adjoint"):
+            getattr(L, name).argtypes = [P, vp]
+            getattr(L, name).restype = None
+        L.ora_step.argtypes = [P, vp, ctypes.c_long]
+        L.ora_step.restype = None
+        L.ora_renorm.argtypes = [P, vp]
+        L.ora_renorm.restype = ctypes.c_int
+        L.ora_norms.argtypes = [P, vp, vp]
+        L.ora_norms.restype = None
+        L.ora_renorm_factors.argtypes = [P, vp, vp]
+        L.ora_renorm_factors.restype = ctypes.c_int
+        L.ora_uses_fixed_m.argtypes = [P]
+        L.ora_uses_fixed_m.restype = ctypes.c_int
+        L.ora_observables.argtypes = [P, vp, vp]
+        L.ora_observables.restype = None
+        L.ora_apply_hso.argtypes = [P, vp, vp]
+        L.ora_apply_hso.restype = None
+        L.ora_step_adjoint.argtypes = [P, vp, vp, ctypes.POINTER(ctypes.c_double)]
+        L.ora_step_adjoint.restype = ctypes.c_int
+        L.ora_num_threads.argtypes = []
+        L.ora_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _arr(cfg: Cfg, psi) -> np.ndarray:
+    a = np.array(psi, dtype=np.complex128, order="C", copy=True)
+    if a.shape != cfg.shape():
+        raise ValueError(f"state shape {a.shape} != {cfg.shape()}")
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _sub(name):
+    def f(cfg: Cfg, psi):
+        a = _arr(cfg, psi)
+        cc = cfg.c()
+        getattr(lib(), name)(ctypes.byref(cc), _ptr(a))
+        return a
+    f.__name__ = name
+    return f
+
+
+calcnu = _sub("ora_calcnu")
+herm = _sub("ora_herm")
+so = _sub("ora_so")
+cn_x = _sub("ora_cn_x")
+cn_y = _sub("ora_cn_y")
+cn_x_adjoint = _sub("ora_cn_x_adjoint")
+cn_y_adjoint = _sub("ora_cn_y_adjoint")
+pointwise_dual_value = _sub("ora_pointwise_dual_value")
+
+
+def step(cfg: Cfg, psi, nsteps: int = 1) -> np.ndarray:
+    """``nsteps`` full SS-CN steps (CALCNU, HERM, SO, LUX, LUY, RENORM)."""
+    a = _arr(cfg, psi)
+    cc = cfg.c()
+    lib().ora_step(ctypes.byref(cc), _ptr(a), int(nsteps))
+    return a
+
+
+def renorm(cfg: Cfg, psi):
+    a = _arr(cfg, psi)
+    cc = cfg.c()
+    fb = lib().ora_renorm(ctypes.byref(cc), _ptr(a))
+    return a, fb
+
+
+def norms(cfg: Cfg, psi) -> np.ndarray:
+    a = _arr(cfg, psi)
+    out = np.zeros(3)
+    cc = cfg.c()
+    lib().ora_norms(ctypes.byref(cc), _ptr(a), _ptr(out))
+    return out
+
+
+def renorm_factors(cfg: Cfg, N):
+    n = np.ascontiguousarray(N, dtype=np.float64)
+    d = np.zeros(3)
+    cc = cfg.c()
+    fb = lib().ora_renorm_factors(ctypes.byref(cc), _ptr(n), _ptr(d))
+    return d, fb
+
+
+def uses_fixed_m(cfg: Cfg) -> bool:
+    cc = cfg.c()
+    return bool(lib().ora_uses_fixed_m(ctypes.byref(cc)))
+
+
+def observables(cfg: Cfg, psi) -> dict:
+    a = _arr(cfg, psi)
+    out = np.zeros(16)
+    cc = cfg.c()
+    lib().ora_observables(ctypes.byref(cc), _ptr(a), _ptr(out))
+    return dict(zip(OBS_NAMES, out.tolist()))
+
+
+def apply_hso(cfg: Cfg, psi) -> np.ndarray:
+    a = _arr(cfg, psi)
+    out = np.zeros_like(a)
+    cc = cfg.c()
+    lib().ora_apply_hso(ctypes.byref(cc), _ptr(a), _ptr(out))
+    return out
+
+
+def step_adjoint(cfg: Cfg, psi_n, lam):
+    """One real-time step backwards: returns (dL/dpsi^n, dL/dOmega of this step)."""
+    a = _arr(cfg, psi_n)
+    l = _arr(cfg, lam)
+    dom = ctypes.c_double(0.0)
+    cc = cfg.c()
+    rc = lib().ora_step_adjoint(ctypes.byref(cc), _ptr(a), _ptr(l), ctypes.byref(dom))
+    if rc != 0:
+        raise ValueError("adjoint is defined for real time only")
+    return l, dom.value
+
+
+def num_threads() -> int:
+    return int(lib().ora_num_threads())
