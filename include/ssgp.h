@@ -1,0 +1,193 @@
+/*
+ * ssgp.h -- C ABI of the MI355X split-step Crank-Nicolson (SS-CN) stepper for
+ * the spin-1 spin-orbit- and Rabi-coupled Gross-Pitaevskii equations of
+ * arXiv:2009.13507 (Eqs. (1)-(2), App. A).
+ *
+ * One step n -> n+1 applies, in this order, with k = i (real time) or k = 1
+ * (imaginary time, Delta -> -i Delta):
+ *   CALCNU  psi_j <- exp(-k dt phi_j) psi_j, phi_j the square brackets of
+ *           Eqs. (1)-(2) with V = (x^2 + kappa^2 y^2)/2, densities of the input;
+ *   HERM    psi <- exp(-k dt A) psi with the 3x3 Hermitian A of App. A,
+ *           Eq. (eq:nu), a = c2 psi_{-1}^* psi_0 + Omega/sqrt2,
+ *           b = c2 psi_0^* psi_{+1} + Omega/sqrt2 (frozen at the input);
+ *   SO      psi <- psi - k dt H_SO psi, explicit, central differences
+ *           (App. A, Eqs. (p1)-(p2); the H_SO forms of Sec. 2);
+ *   LUX/LUY Crank-Nicolson kinetic steps along x then y:
+ *           (I + k dt/2 T) psi' = (I - k dt/2 T) psi, T = -1/2 d^2 on the
+ *           three-point stencil with zero values outside the box (Table 1);
+ *   RENORM  imaginary time only: psi_j <- d_j psi_j, d_j of App. A
+ *           Eq. (DJ) (fixed magnetisation m) or Eq. (DJ2) (norm only).
+ *
+ * Data layout.  A state is 3 planes (components +1, 0, -1) of ny rows of nx
+ * points, x fastest: element (j, iy, ix) at index (j*ny + iy)*nx + ix, as
+ * interleaved (re, im) pairs: complex128 (SSGP_C128) or complex64
+ * (SSGP_C64).  1D grids use ny = 1.  Grid points are x_i = -nx dx/2 + i dx
+ * and y_i = -ny dy/2 + i dy.
+ *
+ * Ownership.  State buffers are device memory owned by the caller (e.g. a
+ * torch tensor); the library keeps borrowed pointers and never frees them.
+ * The library owns its workspace (coefficient tables, reduction partials)
+ * and frees it in ssgp_destroy / ssgp_destroy_batch.
+ *
+ * Streams.  Every call is enqueued on the HIP stream given at creation and
+ * returns without waiting, except ssgp_observables, ssgp_batch_observables
+ * and ssgp_omega_grad, which synchronise that stream.
+ *
+ * Errors.  Every entry point returns SSGP_OK (0) or a negative code and never
+ * throws; ssgp_last_error() returns the message of the calling thread's last
+ * error.  Invalid arguments leave the object unchanged.
+ */
+#ifndef SSGP_H
+#define SSGP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssgp_grid_s *ssgp_grid;
+typedef struct ssgp_batch_s *ssgp_batch;
+
+enum ssgp_status {
+    SSGP_OK = 0,
+    SSGP_EINVAL = -1,      /* invalid argument or unsupported combination   */
+    SSGP_ENOMEM = -2,      /* device or host allocation failed              */
+    SSGP_EDEVICE = -3,     /* a HIP call failed                             */
+    SSGP_ESTATE = -4,      /* call out of order (e.g. no parameters set)    */
+    SSGP_ENONFINITE = -5   /* a reduction met NaN or Inf in the state       */
+};
+
+enum ssgp_dtype { SSGP_C128 = 0, SSGP_C64 = 1 };
+
+/* Spin-orbit forms (OPT_SO of Table 2).  1D: gamma p_x Sigma_{x,y,z}.
+ * 2D: gamma (eta p_y Sigma_x - p_x Sigma_y) with eta = 1 (Rashba),
+ * -1 (Dresselhaus), 0 (equal mixture); SSGP_SO_PX_SX is also accepted in 2D
+ * (x derivative only).  gamma p_x Sigma_y uses the Hermitian form derived
+ * from Sigma_y of Eq. (3): f_{+-1} = -+ gamma~ d_x psi_0,
+ * g = gamma~ d_x (psi_{+1} - psi_{-1}). */
+enum ssgp_so {
+    SSGP_SO_NONE = 0, SSGP_SO_PX_SX = 1, SSGP_SO_PX_SY = 2, SSGP_SO_PX_SZ = 3,
+    SSGP_SO_RASHBA = 4, SSGP_SO_DRESSELHAUS = 5, SSGP_SO_ERD = 6
+};
+
+/* RENORM rule.  AUTO: Eq. (DJ) with m = mag0 when Omega = 0 and the
+ * spin-orbit term commutes with Sigma_z (none, p_x Sigma_z, or gamma = 0),
+ * else Eq. (DJ2).  Eq. (DJ) falls back to Eq. (DJ2) when |m| >= 1, N_{+1} or
+ * N_{-1} is zero, or a radicand is negative. */
+enum ssgp_renorm { SSGP_RENORM_AUTO = 0, SSGP_RENORM_NORM = 1, SSGP_RENORM_FIXED_M = 2 };
+
+typedef struct {
+    double c0, c2;     /* density couplings of Eqs. (1)-(2)                 */
+    double gamma;      /* spin-orbit strength                              */
+    double omega;      /* Rabi strength Omega                              */
+    double kappa;      /* trap aspect ratio in V = (x^2 + kappa^2 y^2)/2     */
+    double dt;         /* time step Delta > 0                              */
+    double mag0;       /* magnetisation m for Eq. (DJ)                     */
+    int so;            /* enum ssgp_so                                     */
+    int renorm;        /* enum ssgp_renorm                                 */
+} ssgp_params;
+
+/* Observables of the current state (Eqs. (4)-(5), rectangle rule):
+ * N[j] = dA sum |psi_j|^2 (j = +1, 0, -1), Ntot, M = N[0] - N[2], energy E
+ * of Eq. (5) with parts {kinetic, trap, c0, c2, Rabi, spin-orbit}; the
+ * kinetic part is the forward difference over every link including the two
+ * links to the zero ghosts of each line; rms[j] = sqrt(sum r^2 rho_j /
+ * sum rho_j) (0 for an empty component), rms_tot for the total density. */
+typedef struct {
+    double N[3], Ntot, M, E, E_parts[6], rms[3], rms_tot;
+} ssgp_obs;
+
+/* Creates a grid bound to the caller's state buffer psi_dev (3*ny*nx complex
+ * elements of dtype, device memory, must outlive the grid) and stream
+ * hip_stream (a hipStream_t, or NULL for the default stream).
+ * dim = 1 (ny must be 1) or 2.  nx, ny >= 1; ny <= 2048; nx <= 2048 (C128) or 4096
+ * (C64) since one row of all three components is staged in LDS.
+ * dx > 0, dy > 0 (dy ignored in 1D).  On success *out owns the workspace. */
+int ssgp_create_grid(int dim, int nx, int ny, double dx, double dy, int dtype,
+                     void *psi_dev, void *hip_stream, ssgp_grid *out);
+
+/* Rebinds the state buffer (same shape and dtype). */
+int ssgp_set_state(ssgp_grid g, void *psi_dev);
+
+/* Validates and stores the model parameters (Table 2: C_0, C_2, OPT_SO,
+ * GAM0, OMEGA0, MAG_0, DT).  EINVAL for dt <= 0, non-finite values, an
+ * unknown so/renorm value, a y-dependent SO form on a 1D grid, a 1D-only SO
+ * form (p_x Sigma_y, p_x Sigma_z) on a 2D grid, or |mag0| > 1. */
+int ssgp_set_params(ssgp_grid g, const ssgp_params *p);
+
+/* Piecewise-constant Rabi control for real-time steps: the step with index
+ * n (see ssgp_set_step_index) uses omega[n / steps_per_seg] (clamped to the
+ * last segment).  nseg = 0 removes the schedule (then params.omega is used).
+ * The array is copied. */
+int ssgp_set_omega_schedule(ssgp_grid g, const double *omega, int nseg, int steps_per_seg);
+
+/* Index of the next real-time step (for the Omega schedule); real-time
+ * steps advance it, adjoint steps move it back. */
+int ssgp_set_step_index(ssgp_grid g, long long n);
+long long ssgp_get_step_index(ssgp_grid g);
+
+/* nsteps >= 0 full imaginary-time steps on the bound state, in place;
+ * RENORM after every step; the state is normalised on return. */
+int ssgp_step_imag(ssgp_grid g, int nsteps);
+
+/* nsteps >= 0 full real-time steps on the bound state, in place. */
+int ssgp_step_real(ssgp_grid g, int nsteps);
+
+/* nsteps real-time steps starting from src_dev, writing the state after step
+ * k (k = 1..nsteps) to dst_dev + (k-1) * (3*ny*nx) elements.  src_dev is not
+ * modified; the bound state is not used.  Advances the step index. */
+int ssgp_step_real_seq(ssgp_grid g, const void *src_dev, void *dst_dev, int nsteps);
+
+/* Observables of the bound state; synchronises the stream.  Returns
+ * SSGP_ENONFINITE (with *out filled) when the norm is NaN or Inf. */
+int ssgp_observables(ssgp_grid g, ssgp_obs *out);
+
+/* Adjoint of real-time steps (reverse-mode derivative in the convention
+ * grad = dL/dRe(psi) + i dL/dIm(psi)).  states_dev holds the nsteps step
+ * inputs psi^{n0}, ..., psi^{n0+nsteps-1} contiguously, where n0 + nsteps is
+ * the current step index; lambda_dev holds dL/dpsi^{n0+nsteps} on entry and
+ * dL/dpsi^{n0} on exit (in place).  Per step, in reverse order: CN_y^H,
+ * CN_x^H, SO^H = I + i dt H_SO, then the transposed Jacobian of the
+ * pointwise HERM o CALCNU map recomputed from the step input.  The
+ * derivative of L with respect to each step's Omega is accumulated on the
+ * device per schedule segment (read with ssgp_omega_grad).  Moves the step
+ * index back by nsteps. */
+int ssgp_step_real_adjoint(ssgp_grid g, const void *states_dev, void *lambda_dev, int nsteps);
+
+/* Copies the accumulated dL/dOmega per segment (nseg values, one value when
+ * no schedule is set) to out and, if reset != 0, clears the accumulators.
+ * Synchronises the stream. */
+int ssgp_omega_grad(ssgp_grid g, double *out, int nseg, int reset);
+
+int ssgp_destroy(ssgp_grid g);
+
+/* Batched imaginary-time stepping of n independent 2D grids held in one
+ * device pool: grid i is nx[i] x ny[i] with spacing dx[i] (dy = dx), state at
+ * pool_dev + offsets[i] elements (3*ny*nx elements each), parameters p[i].
+ * The arrays are copied. */
+int ssgp_create_batch(int n, const int *nx, const int *ny, const double *dx,
+                      const ssgp_params *p, int dtype, void *pool_dev,
+                      const long long *offsets, void *hip_stream, ssgp_batch *out);
+
+/* nsteps imaginary-time steps of every grid of the batch, as one persistent
+ * kernel launch (replayed from a HIP graph) with device-wide barriers between
+ * the x and y sweeps. */
+int ssgp_batch_step_imag(ssgp_batch b, int nsteps);
+
+/* The same steps with one launch per sweep and instance (for comparison). */
+int ssgp_batch_step_imag_serial(ssgp_batch b, int nsteps);
+
+/* Observables of every grid (out has n entries); synchronises the stream. */
+int ssgp_batch_observables(ssgp_batch b, ssgp_obs *out);
+
+int ssgp_destroy_batch(ssgp_batch b);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *ssgp_last_error(void);
+
+/* Library version string. */
+const char *ssgp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSGP_H */

@@ -1,0 +1,754 @@
+// ssgp.hip -- host runtime and C ABI of the MI355X SS-CN stepper
+// (declarations and contracts in include/ssgp.h).
+//
+// A grid owns: the Crank-Nicolson coefficient tables ("COEF" of Table 1 in
+// the paper) per axis and propagation mode, the reduction workspace, the
+// Omega schedule and the adjoint accumulators.  States stay in the caller's
+// buffers.  All work is enqueued on the grid's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ssgp.h"
+#include "adjoint_kernels.hpp"
+#include "batch_kernels.hpp"
+#include "obs_kernels.hpp"
+#include "step_kernels.hpp"
+
+using namespace ssgp;
+using cd = std::complex<double>;
+
+// ------------------------------------------------------------- errors ---
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(SSGP_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+#define SSGP_TRY(expr)                                                                       \
+    do {                                                                                     \
+        int rc_ = (expr);                                                                    \
+        if (rc_ != SSGP_OK) return rc_;                                                      \
+    } while (0)
+
+extern "C" const char *ssgp_last_error(void) { return g_err.c_str(); }
+extern "C" const char *ssgp_version(void) { return "ssgp 0.1 (gfx950)"; }
+
+// --------------------------------------------------- device buffers -----
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int ensure(size_t b) {
+        if (b <= bytes) return SSGP_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (hipMalloc(&p, b) != hipSuccess) return fail(SSGP_ENOMEM, "hipMalloc(%zu) failed", b);
+        bytes = b;
+        return SSGP_OK;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ------------------------------------------------- CN coefficient tables -
+// (I + sT) with T = tridiag(-1/(2h^2), 1/h^2, -1/(2h^2)): diagonal
+// d = 1 + s/h^2, off-diagonal o = -s/(2h^2).  Thomas pivots m_0 = d,
+// m_i = d - o c'_{i-1}; inv_i = 1/m_i, c'_i = o inv_i.  Chunk products
+// A_k = prod_{i in chunk k} (-c'_i) (1 for empty chunks).
+struct CNHost {
+    std::vector<cd> inv, cp, chunkA;
+    cd rdiag, roff;
+};
+
+static CNHost cn_tables(int n, double h, cd s, int L, int nchunks) {
+    CNHost t;
+    const cd d = 1.0 + s / (h * h), o = -s / (2.0 * h * h);
+    t.inv.resize(n);
+    t.cp.resize(n);
+    t.inv[0] = 1.0 / d;
+    t.cp[0] = o * t.inv[0];
+    for (int i = 1; i < n; ++i) {
+        const cd m = d - o * t.cp[i - 1];
+        t.inv[i] = 1.0 / m;
+        t.cp[i] = o * t.inv[i];
+    }
+    t.chunkA.assign(nchunks, cd(1.0, 0.0));
+    for (int k = 0; k < nchunks; ++k)
+        for (int i = k * L; i < std::min(n, (k + 1) * L); ++i) t.chunkA[k] *= -t.cp[i];
+    t.rdiag = 1.0 - s / (h * h);
+    t.roff = s / (2.0 * h * h);
+    return t;
+}
+
+template <typename R> struct CNDev {
+    DevBuf buf;  // inv[n] | cp[n] | chunkA[nchunks]
+    int n = 0, L = 0, nchunks = 0;
+    cx<R> rdiag{}, roff{};
+    const cx<R> *inv() const { return buf.as<cx<R>>(); }
+    const cx<R> *cp() const { return buf.as<cx<R>>() + n; }
+    const cx<R> *chunkA() const { return buf.as<cx<R>>() + 2 * n; }
+};
+
+template <typename R> static cx<R> tor(cd v) { return cx<R>{(R)v.real(), (R)v.imag()}; }
+
+template <typename R>
+static int upload_cn(CNDev<R> &dst, const CNHost &h, int n, int L, int nchunks, hipStream_t st) {
+    std::vector<cx<R>> host(2 * n + nchunks);
+    for (int i = 0; i < n; ++i) {
+        host[i] = tor<R>(h.inv[i]);
+        host[n + i] = tor<R>(h.cp[i]);
+    }
+    for (int k = 0; k < nchunks; ++k) host[2 * n + k] = tor<R>(h.chunkA[k]);
+    SSGP_TRY(dst.buf.ensure(host.size() * sizeof(cx<R>)));
+    HIP_TRY(hipMemcpyAsync(dst.buf.p, host.data(), host.size() * sizeof(cx<R>), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    dst.n = n;
+    dst.L = L;
+    dst.nchunks = nchunks;
+    dst.rdiag = tor<R>(h.rdiag);
+    dst.roff = tor<R>(h.roff);
+    return SSGP_OK;
+}
+
+static int pow2_at_least(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// chunk length of an x line handled by one 64-lane wavefront
+static int x_chunk(int nx) { return pow2_at_least((nx + 63) / 64); }
+
+// y-pass shape: TX columns per workgroup, chunks of LY rows, P chunks.
+constexpr int YTX = 8;
+struct YShape {
+    int L, P, threads;
+};
+static YShape y_shape(int ny) {
+    // smallest chunk (8, 16 or 32 rows) that fits the column in 512 lanes
+    int L = 8;
+    while (L < 32 && YTX * ((ny + L - 1) / L) > YPASS_MAX_THREADS) L <<= 1;
+    int P = (ny + L - 1) / L;
+    const int per_wave = 64 / YTX;
+    P = (P + per_wave - 1) / per_wave * per_wave;
+    return {L, P, P * YTX};
+}
+
+// ------------------------------------------------------------ SO forms --
+// H_SO psi_j = sum_j' hx[j][j'] d_x psi_j' + hy[j][j'] d_y psi_j' (p = -i d).
+struct SOForm {
+    cd hx[9], hy[9];
+};
+
+static void spin_matrices(cd Sx[9], cd Sy[9], cd Sz[9]) {
+    const double r = 1.0 / std::sqrt(2.0);
+    const cd I(0.0, 1.0);
+    const cd sx[9] = {0, r, 0, r, 0, r, 0, r, 0};
+    const cd sy[9] = {0, -I * r, 0, I * r, 0, -I * r, 0, I * r, 0};
+    const cd sz[9] = {1, 0, 0, 0, 0, 0, 0, 0, -1};
+    for (int q = 0; q < 9; ++q) {
+        Sx[q] = sx[q];
+        Sy[q] = sy[q];
+        Sz[q] = sz[q];
+    }
+}
+
+static SOForm so_form(int so, double gamma) {
+    SOForm f;
+    for (int q = 0; q < 9; ++q) f.hx[q] = f.hy[q] = 0.0;
+    cd Sx[9], Sy[9], Sz[9];
+    spin_matrices(Sx, Sy, Sz);
+    const cd mi(0.0, -1.0);
+    switch (so) {
+    case SSGP_SO_PX_SX:
+        for (int q = 0; q < 9; ++q) f.hx[q] = mi * gamma * Sx[q];
+        break;
+    case SSGP_SO_PX_SY:
+        for (int q = 0; q < 9; ++q) f.hx[q] = mi * gamma * Sy[q];
+        break;
+    case SSGP_SO_PX_SZ:
+        for (int q = 0; q < 9; ++q) f.hx[q] = mi * gamma * Sz[q];
+        break;
+    case SSGP_SO_RASHBA:
+    case SSGP_SO_DRESSELHAUS:
+    case SSGP_SO_ERD: {
+        // gamma (eta p_y Sigma_x - p_x Sigma_y)
+        const double eta = so == SSGP_SO_RASHBA ? 1.0 : (so == SSGP_SO_DRESSELHAUS ? -1.0 : 0.0);
+        for (int q = 0; q < 9; ++q) {
+            f.hy[q] = mi * gamma * eta * Sx[q];
+            f.hx[q] = -mi * gamma * Sy[q];
+        }
+        break;
+    }
+    default:
+        break;
+    }
+    return f;
+}
+
+static unsigned nz_mask(const cd *m) {
+    unsigned b = 0;
+    for (int q = 0; q < 9; ++q)
+        if (m[q] != cd(0.0, 0.0)) b |= 1u << q;
+    return b;
+}
+
+// --------------------------------------------------------------- grid ---
+enum { MODE_REAL = 0, MODE_IMAG = 1, MODE_ADJ = 2, NMODES = 3 };
+
+struct GridCore {
+    int dim = 2, nx = 0, ny = 1;
+    double dx = 0, dy = 0;
+    int dtype = SSGP_C128;
+    void *psi = nullptr;
+    hipStream_t stream = nullptr;
+    ssgp_params p{};
+    bool have_params = false;
+    std::vector<double> omega_sched;
+    int steps_per_seg = 1;
+    long long step_index = 0;
+    DevBuf partials, renorm, obs_partials, obs_out, scratch, omega_acc, adj_partials;
+    int built_mode_mask = 0;
+};
+
+template <typename R> struct Tables {
+    CNDev<R> x[NMODES], y[NMODES];
+};
+
+struct ssgp_grid_s : GridCore {
+    Tables<double> t64;
+    Tables<float> t32;
+};
+
+static size_t elem_bytes(int dtype) { return dtype == SSGP_C64 ? 8 : 16; }
+static double darea(const GridCore &g) { return g.dim == 2 ? g.dx * g.dy : g.dx; }
+static long long plane_of(const GridCore &g) { return (long long)g.nx * (g.dim == 2 ? g.ny : 1); }
+
+static cd kfac(int mode) { return mode == MODE_IMAG ? cd(1.0, 0.0) : cd(0.0, 1.0); }
+// s = k dt / 2 of the Crank-Nicolson factor; the adjoint of a real-time
+// step solves with the conjugate matrices.
+static cd cn_s(int mode, double dt) {
+    const cd s = 0.5 * kfac(mode) * dt;
+    return mode == MODE_ADJ ? std::conj(s) : s;
+}
+
+template <typename R> static Tables<R> &tables(ssgp_grid g);
+template <> Tables<double> &tables<double>(ssgp_grid g) { return g->t64; }
+template <> Tables<float> &tables<float>(ssgp_grid g) { return g->t32; }
+
+template <typename R> static int build_tables(ssgp_grid g, int mode) {
+    if (g->built_mode_mask & (1 << mode)) return SSGP_OK;
+    Tables<R> &T = tables<R>(g);
+    const cd s = cn_s(mode, g->p.dt);
+    const int Lx = x_chunk(g->nx);
+    SSGP_TRY(upload_cn<R>(T.x[mode], cn_tables(g->nx, g->dx, s, Lx, 64), g->nx, Lx, 64, g->stream));
+    if (g->dim == 2) {
+        const YShape ys = y_shape(g->ny);
+        SSGP_TRY(upload_cn<R>(T.y[mode], cn_tables(g->ny, g->dy, s, ys.L, ys.P), g->ny, ys.L, ys.P, g->stream));
+    }
+    g->built_mode_mask |= 1 << mode;
+    return SSGP_OK;
+}
+
+static bool uses_fixed_m(const ssgp_params &p) {
+    if (p.renorm == SSGP_RENORM_NORM) return false;
+    if (p.renorm == SSGP_RENORM_FIXED_M) return true;
+    const bool commutes = p.so == SSGP_SO_NONE || p.so == SSGP_SO_PX_SZ || p.gamma == 0.0;
+    return p.omega == 0.0 && commutes;
+}
+
+static bool so_has_y(int so) { return so == SSGP_SO_RASHBA || so == SSGP_SO_DRESSELHAUS || so == SSGP_SO_ERD; }
+
+static double omega_at(const GridCore &g, long long n) {
+    if (g.omega_sched.empty()) return g.p.omega;
+    long long s = n / g.steps_per_seg;
+    if (s < 0) s = 0;
+    if (s >= (long long)g.omega_sched.size()) s = (long long)g.omega_sched.size() - 1;
+    return g.omega_sched[(size_t)s];
+}
+
+template <typename R> static Model<R> model(const GridCore &g, int mode, double omega) {
+    Model<R> m;
+    m.c0 = (R)g.p.c0;
+    m.c2 = (R)g.p.c2;
+    m.dt = (R)g.p.dt;
+    m.om_t = (R)(omega / std::sqrt(2.0));
+    m.kappa2 = (R)(g.p.kappa * g.p.kappa);
+    m.imag = mode == MODE_IMAG ? 1 : 0;
+    return m;
+}
+
+// ------------------------------------------------------------ launches --
+template <typename R, int L>
+static int launch_x_L(const GridCore &g, const XArgs<R> &a) {
+    const int ld = srow<L>(g.nx);
+    const size_t lds = (size_t)(a.so_y ? 6 : 3) * ld * sizeof(cx<R>);
+    if (lds > 160 * 1024) return fail(SSGP_EINVAL, "row of nx=%d does not fit in LDS", g.nx);
+    if (lds > 64 * 1024)
+        HIP_TRY(hipFuncSetAttribute((const void *)xpass_kernel<R, L>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int rows = g.dim == 2 ? g.ny : 1;
+    xpass_kernel<R, L><<<rows, XPASS_THREADS, lds, g.stream>>>(a);
+    HIP_TRY(hipGetLastError());
+    return SSGP_OK;
+}
+
+template <typename R> static int launch_x(const GridCore &g, const XArgs<R> &a, int L) {
+    switch (L) {
+    case 1: return launch_x_L<R, 1>(g, a);
+    case 2: return launch_x_L<R, 2>(g, a);
+    case 4: return launch_x_L<R, 4>(g, a);
+    case 8: return launch_x_L<R, 8>(g, a);
+    case 16: return launch_x_L<R, 16>(g, a);
+    case 32: return launch_x_L<R, 32>(g, a);
+    case 64: return launch_x_L<R, 64>(g, a);
+    default: return fail(SSGP_EINVAL, "unsupported x chunk %d", L);
+    }
+}
+
+template <typename R, int L>
+static int launch_y_L(const GridCore &g, const YArgs<R> &a, const YShape &ys) {
+    dim3 grid((g.nx + YTX - 1) / YTX, 3);
+    ypass_kernel<R, L, YTX><<<grid, ys.threads, 0, g.stream>>>(a);
+    HIP_TRY(hipGetLastError());
+    return SSGP_OK;
+}
+
+template <typename R> static int launch_y(const GridCore &g, const YArgs<R> &a, const YShape &ys) {
+    switch (ys.L) {
+    case 8: return launch_y_L<R, 8>(g, a, ys);
+    case 16: return launch_y_L<R, 16>(g, a, ys);
+    case 32: return launch_y_L<R, 32>(g, a, ys);
+    default: return fail(SSGP_EINVAL, "unsupported y chunk %d", ys.L);
+    }
+}
+
+template <typename R>
+static void fill_so(XArgs<R> &a, const GridCore &g, int mode) {
+    const SOForm f = so_form(g.p.so, g.p.gamma);
+    const cd k = kfac(mode);
+    // psi' = psi - k dt H psi with central differences
+    cd kd = k * g.p.dt;
+    if (mode == MODE_ADJ) kd = -kd;  // S^H = I + i dt H in real time
+    for (int q = 0; q < 9; ++q) {
+        a.qx[q] = tor<R>(-kd * f.hx[q] / (2.0 * g.dx));
+        a.qy[q] = tor<R>(-kd * f.hy[q] / (2.0 * g.dy));
+    }
+    a.qxmask = g.p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hx);
+    a.qymask = g.p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hy);
+}
+
+template <typename R>
+static XArgs<R> x_args(ssgp_grid g, int mode, const void *src, void *dst, double omega, const double *dscale) {
+    Tables<R> &T = tables<R>(g);
+    XArgs<R> a{};
+    a.src = static_cast<const cx<R> *>(src);
+    a.dst = static_cast<cx<R> *>(dst);
+    a.nx = g->nx;
+    a.ny = g->dim == 2 ? g->ny : 1;
+    a.plane = plane_of(*g);
+    a.dx = (R)g->dx;
+    a.dy = (R)(g->dim == 2 ? g->dy : 0.0);
+    a.x0 = (R)(-0.5 * g->nx * g->dx);
+    a.y0 = (R)(g->dim == 2 ? -0.5 * g->ny * g->dy : 0.0);
+    a.m = model<R>(*g, mode, omega);
+    a.dscale = dscale;
+    a.pointwise = 1;
+    a.inv = T.x[mode].inv();
+    a.cp = T.x[mode].cp();
+    a.chunkA = T.x[mode].chunkA();
+    a.rdiag = T.x[mode].rdiag;
+    a.roff = T.x[mode].roff;
+    fill_so(a, *g, mode);
+    a.so_y = 0;
+    return a;
+}
+
+template <typename R>
+static YArgs<R> y_args(ssgp_grid g, int mode, void *psi, double *partials) {
+    Tables<R> &T = tables<R>(g);
+    YArgs<R> a{};
+    a.psi = static_cast<cx<R> *>(psi);
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.plane = plane_of(*g);
+    a.inv = T.y[mode].inv();
+    a.cp = T.y[mode].cp();
+    a.chunkA = T.y[mode].chunkA();
+    a.rdiag = T.y[mode].rdiag;
+    a.roff = T.y[mode].roff;
+    a.norm_partials = partials;
+    return a;
+}
+
+static RenormSpec renorm_spec(const GridCore &g) {
+    RenormSpec sp;
+    sp.fixed_m = uses_fixed_m(g.p) ? 1 : 0;
+    sp.m = g.p.mag0;
+    sp.dA = darea(g);
+    return sp;
+}
+
+template <typename R> static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps);
+
+static int ew_blocks(long long n) { return (int)std::min<long long>((n + 255) / 256, 2048); }
+
+// One 2D step from src into dst (dst may equal src except with a
+// y-derivative SO form).  Imaginary time: dscale are the RENORM factors of
+// the previous step (nullptr for none); the norms of the result are reduced
+// into g->renorm.
+template <typename R>
+static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omega, const double *dscale) {
+    const bool imag = mode == MODE_IMAG;
+    const int Lx = x_chunk(g->nx);
+    const YShape ys = y_shape(g->ny);
+    const int ntiles = (g->nx + YTX - 1) / YTX;
+    if (so_has_y(g->p.so) && g->p.gamma != 0.0) {
+        // pointwise pass in place on src's copy in scratch, then SO(x,y) + CN_x
+        const size_t bytes = (size_t)3 * plane_of(*g) * sizeof(cx<R>);
+        SSGP_TRY(g->scratch.ensure(bytes));
+        if (src != g->scratch.p)
+            HIP_TRY(hipMemcpyAsync(g->scratch.p, src, bytes, hipMemcpyDeviceToDevice, g->stream));
+        PArgs<R> pa{};
+        pa.psi = g->scratch.as<cx<R>>();
+        pa.nx = g->nx;
+        pa.ny = g->ny;
+        pa.plane = plane_of(*g);
+        pa.dx = (R)g->dx;
+        pa.dy = (R)g->dy;
+        pa.x0 = (R)(-0.5 * g->nx * g->dx);
+        pa.y0 = (R)(-0.5 * g->ny * g->dy);
+        pa.m = model<R>(*g, mode, omega);
+        pa.dscale = dscale;
+        pointwise_kernel<R><<<ew_blocks(pa.plane), 256, 0, g->stream>>>(pa);
+        HIP_TRY(hipGetLastError());
+        XArgs<R> xa = x_args<R>(g, mode, g->scratch.p, dst, omega, nullptr);
+        xa.pointwise = 0;
+        xa.so_y = 1;
+        SSGP_TRY(launch_x<R>(*g, xa, Lx));
+    } else {
+        XArgs<R> xa = x_args<R>(g, mode, src, dst, omega, dscale);
+        SSGP_TRY(launch_x<R>(*g, xa, Lx));
+    }
+    YArgs<R> ya = y_args<R>(g, mode, dst, imag ? g->partials.as<double>() : nullptr);
+    SSGP_TRY(launch_y<R>(*g, ya, ys));
+    if (imag) {
+        renorm_finalize_kernel<<<1, 256, 0, g->stream>>>(g->partials.as<double>(), ntiles, renorm_spec(*g),
+                                                         g->renorm.as<double>());
+        HIP_TRY(hipGetLastError());
+    }
+    return SSGP_OK;
+}
+
+template <typename R, int L>
+static int launch_1d_L(ssgp_grid g, int mode, void *psi, int nsteps, double omega) {
+    Tables<R> &T = tables<R>(g);
+    Args1D<R> a{};
+    a.psi = static_cast<cx<R> *>(psi);
+    a.nx = g->nx;
+    a.nsteps = nsteps;
+    a.dx = (R)g->dx;
+    a.x0 = (R)(-0.5 * g->nx * g->dx);
+    a.m = model<R>(*g, mode, omega);
+    a.inv = T.x[mode].inv();
+    a.cp = T.x[mode].cp();
+    a.chunkA = T.x[mode].chunkA();
+    a.rdiag = T.x[mode].rdiag;
+    a.roff = T.x[mode].roff;
+    XArgs<R> tmp{};
+    fill_so(tmp, *g, mode);
+    for (int q = 0; q < 9; ++q) a.qx[q] = tmp.qx[q];
+    a.qxmask = tmp.qxmask;
+    a.sp = renorm_spec(*g);
+    a.renorm_out = g->renorm.as<double>();
+    const size_t lds = (size_t)3 * srow<L>(g->nx) * sizeof(cx<R>);
+    if (lds > 64 * 1024)
+        HIP_TRY(hipFuncSetAttribute((const void *)step1d_kernel<R, L>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    step1d_kernel<R, L><<<1, XPASS_THREADS, lds, g->stream>>>(a);
+    HIP_TRY(hipGetLastError());
+    return SSGP_OK;
+}
+
+template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int nsteps, double omega) {
+    switch (x_chunk(g->nx)) {
+    case 1: return launch_1d_L<R, 1>(g, mode, psi, nsteps, omega);
+    case 2: return launch_1d_L<R, 2>(g, mode, psi, nsteps, omega);
+    case 4: return launch_1d_L<R, 4>(g, mode, psi, nsteps, omega);
+    case 8: return launch_1d_L<R, 8>(g, mode, psi, nsteps, omega);
+    case 16: return launch_1d_L<R, 16>(g, mode, psi, nsteps, omega);
+    case 32: return launch_1d_L<R, 32>(g, mode, psi, nsteps, omega);
+    case 64: return launch_1d_L<R, 64>(g, mode, psi, nsteps, omega);
+    default: return fail(SSGP_EINVAL, "unsupported 1D chunk");
+    }
+}
+
+template <typename R> static int step_imag_t(ssgp_grid g, int nsteps) {
+    SSGP_TRY(build_tables<R>(g, MODE_IMAG));
+    if (g->dim == 1) return launch_1d<R>(g, MODE_IMAG, g->psi, nsteps, g->p.omega);
+    for (int s = 0; s < nsteps; ++s)
+        SSGP_TRY(step2d<R>(g, MODE_IMAG, g->psi, g->psi, g->p.omega, s == 0 ? nullptr : g->renorm.as<double>()));
+    if (nsteps > 0) {
+        scale_kernel<R><<<ew_blocks(plane_of(*g)), 256, 0, g->stream>>>(static_cast<cx<R> *>(g->psi),
+                                                                        plane_of(*g), g->renorm.as<double>());
+        HIP_TRY(hipGetLastError());
+    }
+    return SSGP_OK;
+}
+
+template <typename R> static int step_real_t(ssgp_grid g, const void *src, void *dst, int nsteps, bool seq) {
+    SSGP_TRY(build_tables<R>(g, MODE_REAL));
+    const size_t state_elems = (size_t)3 * plane_of(*g);
+    if (g->dim == 1) {
+        // 1D: the whole run stays in LDS; split launches where Omega changes
+        int done = 0;
+        const cx<R> *cur = static_cast<const cx<R> *>(src);
+        while (done < nsteps) {
+            int chunk = nsteps - done;
+            if (!g->omega_sched.empty()) {
+                const long long n = g->step_index;
+                const long long seg_end = (n / g->steps_per_seg + 1) * g->steps_per_seg;
+                chunk = (int)std::min<long long>(chunk, seg_end - n);
+            }
+            if (seq) chunk = 1;
+            cx<R> *out = static_cast<cx<R> *>(dst) + (seq ? (size_t)done * state_elems : 0);
+            if (out != cur)
+                HIP_TRY(hipMemcpyAsync(out, cur, state_elems * sizeof(cx<R>), hipMemcpyDeviceToDevice, g->stream));
+            SSGP_TRY(launch_1d<R>(g, MODE_REAL, out, chunk, omega_at(*g, g->step_index)));
+            g->step_index += chunk;
+            done += chunk;
+            cur = out;
+        }
+        return SSGP_OK;
+    }
+    const cx<R> *cur = static_cast<const cx<R> *>(src);
+    for (int s = 0; s < nsteps; ++s) {
+        cx<R> *out = static_cast<cx<R> *>(dst) + (seq ? (size_t)s * state_elems : 0);
+        SSGP_TRY(step2d<R>(g, MODE_REAL, cur, out, omega_at(*g, g->step_index), nullptr));
+        g->step_index += 1;
+        cur = out;
+    }
+    return SSGP_OK;
+}
+
+// ---------------------------------------------------------------- ABI ---
+static int check_params(const GridCore &g, const ssgp_params *p) {
+    if (!p) return fail(SSGP_EINVAL, "params is NULL");
+    const double v[] = {p->c0, p->c2, p->gamma, p->omega, p->kappa, p->dt, p->mag0};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(SSGP_EINVAL, "non-finite parameter");
+    if (!(p->dt > 0)) return fail(SSGP_EINVAL, "dt must be > 0 (got %g)", p->dt);
+    if (p->so < SSGP_SO_NONE || p->so > SSGP_SO_ERD) return fail(SSGP_EINVAL, "unknown so form %d", p->so);
+    if (p->renorm < SSGP_RENORM_AUTO || p->renorm > SSGP_RENORM_FIXED_M)
+        return fail(SSGP_EINVAL, "unknown renorm rule %d", p->renorm);
+    if (g.dim == 1 && so_has_y(p->so)) return fail(SSGP_EINVAL, "y-dependent SO form on a 1D grid");
+    if (g.dim == 2 && (p->so == SSGP_SO_PX_SY || p->so == SSGP_SO_PX_SZ))
+        return fail(SSGP_EINVAL, "SO form %d is defined for 1D grids", p->so);
+    if (std::fabs(p->mag0) > 1.0) return fail(SSGP_EINVAL, "|mag0| must be <= 1");
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_create_grid(int dim, int nx, int ny, double dx, double dy, int dtype, void *psi_dev,
+                                void *hip_stream, ssgp_grid *out) {
+    if (!out) return fail(SSGP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (dim != 1 && dim != 2) return fail(SSGP_EINVAL, "dim must be 1 or 2");
+    if (dtype != SSGP_C128 && dtype != SSGP_C64) return fail(SSGP_EINVAL, "unknown dtype %d", dtype);
+    if (dim == 1) ny = 1;
+    const int nxmax = dtype == SSGP_C128 ? 2048 : 4096;
+    if (nx < 1 || nx > nxmax) return fail(SSGP_EINVAL, "nx must be in [1, %d] (got %d)", nxmax, nx);
+    if (ny < 1 || ny > 2048) return fail(SSGP_EINVAL, "ny must be in [1, 2048] (got %d)", ny);
+    if (!(dx > 0) || !std::isfinite(dx) || (dim == 2 && (!(dy > 0) || !std::isfinite(dy))))
+        return fail(SSGP_EINVAL, "grid spacing must be positive");
+    if (!psi_dev) return fail(SSGP_EINVAL, "psi_dev is NULL");
+    ssgp_grid g = new (std::nothrow) ssgp_grid_s();
+    if (!g) return fail(SSGP_ENOMEM, "host allocation failed");
+    g->dim = dim;
+    g->nx = nx;
+    g->ny = ny;
+    g->dx = dx;
+    g->dy = dim == 2 ? dy : 1.0;
+    g->dtype = dtype;
+    g->psi = psi_dev;
+    g->stream = static_cast<hipStream_t>(hip_stream);
+    const int ntiles = (nx + YTX - 1) / YTX;
+    int rc = g->partials.ensure(sizeof(double) * 3 * ntiles);
+    if (rc == SSGP_OK) rc = g->renorm.ensure(sizeof(double) * 8);
+    if (rc == SSGP_OK) rc = g->obs_partials.ensure(sizeof(double) * OBS_NQ * 1024);
+    if (rc == SSGP_OK) rc = g->obs_out.ensure(sizeof(double) * 16);
+    if (rc == SSGP_OK) rc = g->omega_acc.ensure(sizeof(double) * 1);
+    if (rc != SSGP_OK) {
+        delete g;
+        return rc;
+    }
+    if (hipMemsetAsync(g->omega_acc.p, 0, sizeof(double), g->stream) != hipSuccess) {
+        delete g;
+        return fail(SSGP_EDEVICE, "hipMemsetAsync failed");
+    }
+    *out = g;
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_set_state(ssgp_grid g, void *psi_dev) {
+    if (!g || !psi_dev) return fail(SSGP_EINVAL, "NULL argument");
+    g->psi = psi_dev;
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_set_params(ssgp_grid g, const ssgp_params *p) {
+    if (!g) return fail(SSGP_EINVAL, "grid is NULL");
+    SSGP_TRY(check_params(*g, p));
+    if (!g->have_params || p->dt != g->p.dt) g->built_mode_mask = 0;
+    g->p = *p;
+    g->have_params = true;
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_set_omega_schedule(ssgp_grid g, const double *omega, int nseg, int steps_per_seg) {
+    if (!g) return fail(SSGP_EINVAL, "grid is NULL");
+    if (nseg < 0 || (nseg > 0 && (!omega || steps_per_seg < 1))) return fail(SSGP_EINVAL, "bad schedule");
+    for (int s = 0; s < nseg; ++s)
+        if (!std::isfinite(omega[s])) return fail(SSGP_EINVAL, "non-finite Omega");
+    g->omega_sched.assign(omega, omega + nseg);
+    g->steps_per_seg = nseg > 0 ? steps_per_seg : 1;
+    const size_t n = std::max(1, nseg);
+    SSGP_TRY(g->omega_acc.ensure(sizeof(double) * n));
+    HIP_TRY(hipMemsetAsync(g->omega_acc.p, 0, sizeof(double) * n, g->stream));
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_set_step_index(ssgp_grid g, long long n) {
+    if (!g) return fail(SSGP_EINVAL, "grid is NULL");
+    g->step_index = n;
+    return SSGP_OK;
+}
+
+extern "C" long long ssgp_get_step_index(ssgp_grid g) { return g ? g->step_index : -1; }
+
+extern "C" int ssgp_step_imag(ssgp_grid g, int nsteps) {
+    if (!g) return fail(SSGP_EINVAL, "grid is NULL");
+    if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
+    if (nsteps < 0) return fail(SSGP_EINVAL, "nsteps < 0");
+    return g->dtype == SSGP_C128 ? step_imag_t<double>(g, nsteps) : step_imag_t<float>(g, nsteps);
+}
+
+extern "C" int ssgp_step_real(ssgp_grid g, int nsteps) {
+    if (!g) return fail(SSGP_EINVAL, "grid is NULL");
+    if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
+    if (nsteps < 0) return fail(SSGP_EINVAL, "nsteps < 0");
+    return g->dtype == SSGP_C128 ? step_real_t<double>(g, g->psi, g->psi, nsteps, false)
+                                 : step_real_t<float>(g, g->psi, g->psi, nsteps, false);
+}
+
+extern "C" int ssgp_step_real_seq(ssgp_grid g, const void *src, void *dst, int nsteps) {
+    if (!g || !src || !dst) return fail(SSGP_EINVAL, "NULL argument");
+    if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
+    if (nsteps < 0) return fail(SSGP_EINVAL, "nsteps < 0");
+    return g->dtype == SSGP_C128 ? step_real_t<double>(g, src, dst, nsteps, true)
+                                 : step_real_t<float>(g, src, dst, nsteps, true);
+}
+
+template <typename R> static int observables_t(ssgp_grid g, const void *psi, ssgp_obs *out) {
+    ObsArgs<R> a{};
+    a.psi = static_cast<const cx<R> *>(psi);
+    a.dim = g->dim;
+    a.nx = g->nx;
+    a.ny = g->dim == 2 ? g->ny : 1;
+    a.plane = plane_of(*g);
+    a.dx = g->dx;
+    a.dy = g->dy;
+    a.x0 = -0.5 * g->nx * g->dx;
+    a.y0 = g->dim == 2 ? -0.5 * g->ny * g->dy : 0.0;
+    a.kappa2 = g->p.kappa * g->p.kappa;
+    a.c0 = g->p.c0;
+    a.c2 = g->p.c2;
+    a.om_t = omega_at(*g, g->step_index) / std::sqrt(2.0);
+    const SOForm f = so_form(g->p.so, g->p.gamma);
+    for (int q = 0; q < 9; ++q) {
+        a.hx[q] = cx<double>{f.hx[q].real(), f.hx[q].imag()};
+        a.hy[q] = cx<double>{f.hy[q].real(), f.hy[q].imag()};
+    }
+    a.hxmask = g->p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hx);
+    a.hymask = g->p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hy);
+    a.partials = g->obs_partials.as<double>();
+    const int nb = (int)std::min<long long>((a.plane + 255) / 256, 1024);
+    obs_kernel<R><<<nb, 256, 0, g->stream>>>(a);
+    HIP_TRY(hipGetLastError());
+    obs_finalize_kernel<<<1, 256, 0, g->stream>>>(g->obs_partials.as<double>(), nb, g->obs_out.as<double>());
+    HIP_TRY(hipGetLastError());
+    double h[OBS_NQ];
+    HIP_TRY(hipMemcpyAsync(h, g->obs_out.p, sizeof h, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    const double dA = darea(*g);
+    ssgp_obs o{};
+    for (int j = 0; j < 3; ++j) o.N[j] = h[j] * dA;
+    o.Ntot = o.N[0] + o.N[1] + o.N[2];
+    o.M = o.N[0] - o.N[2];
+    for (int q = 0; q < 6; ++q) o.E_parts[q] = h[6 + q] * dA;
+    o.E = o.E_parts[0] + o.E_parts[1] + o.E_parts[2] + o.E_parts[3] + o.E_parts[4] + o.E_parts[5];
+    for (int j = 0; j < 3; ++j) o.rms[j] = h[j] > 0.0 ? std::sqrt(h[3 + j] / h[j]) : 0.0;
+    const double nt = h[0] + h[1] + h[2];
+    o.rms_tot = nt > 0.0 ? std::sqrt((h[3] + h[4] + h[5]) / nt) : 0.0;
+    *out = o;
+    if (!std::isfinite(o.Ntot) || !std::isfinite(o.E)) return fail(SSGP_ENONFINITE, "state holds NaN or Inf");
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_observables(ssgp_grid g, ssgp_obs *out) {
+    if (!g || !out) return fail(SSGP_EINVAL, "NULL argument");
+    if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
+    return g->dtype == SSGP_C128 ? observables_t<double>(g, g->psi, out) : observables_t<float>(g, g->psi, out);
+}
+
+extern "C" int ssgp_step_real_adjoint(ssgp_grid g, const void *states_dev, void *lambda_dev, int nsteps) {
+    if (!g || !states_dev || !lambda_dev) return fail(SSGP_EINVAL, "NULL argument");
+    if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
+    if (nsteps < 0) return fail(SSGP_EINVAL, "nsteps < 0");
+    return g->dtype == SSGP_C128 ? adjoint_steps<double>(g, states_dev, lambda_dev, nsteps)
+                                 : adjoint_steps<float>(g, states_dev, lambda_dev, nsteps);
+}
+
+extern "C" int ssgp_omega_grad(ssgp_grid g, double *out, int nseg, int reset) {
+    if (!g || !out) return fail(SSGP_EINVAL, "NULL argument");
+    const int have = std::max<int>(1, (int)g->omega_sched.size());
+    if (nseg != have) return fail(SSGP_EINVAL, "nseg must be %d", have);
+    HIP_TRY(hipMemcpyAsync(out, g->omega_acc.p, sizeof(double) * nseg, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    if (reset) HIP_TRY(hipMemsetAsync(g->omega_acc.p, 0, sizeof(double) * nseg, g->stream));
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_destroy(ssgp_grid g) {
+    if (!g) return SSGP_OK;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    else (void)hipDeviceSynchronize();
+    delete g;
+    return SSGP_OK;
+}
+
+#include "adjoint_host.inl"
+#include "batch_host.inl"
