@@ -1,0 +1,179 @@
+"""Benchmark of the SS-CN hot path on one MI355X.
+
+Workload: the 1024^2 FP64 real-time quench (dx = dy = 0.05, dt = 1e-4,
+c0 = 2, c2 = +0.1, gamma = 0.8 with gamma p_x Sigma_x, Omega = 0.2) started
+from the 256^2 imaginary-time ground state interpolated onto the grid, with
+norm, magnetisation, energy and rms sizes taken every 100 steps.  A "step" is
+one full SS-CN time step (CALCNU, HERM, SO, LUX, LUY) of the whole grid.
+
+Prints one JSON line:
+  value      grid-point-steps per second over the timed steps (state resident
+             in HBM when the timed region starts);
+  roofline   the dominant kernel's algorithmic bytes per launch over its mean
+             duration (HIP events on the library's stream during the timed
+             region) against the 8 TB/s HBM peak;
+  cpu_baseline  the CPU oracle on the host cores, on a bounded sample of the
+             same workload (first steps from the same initial state).
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PT_PASS = {"f64": 96, "f32": 48}   # one pass reads and writes 3 complex values
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_xpass_ypass_1024.json")
+KERNEL_SOURCES = ["paper_2009_13507_amd/csrc/step_kernels.hpp", "paper_2009_13507_amd/csrc/cplx.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, npts: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or the kernel source has changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("src_sha") != kernel_source_hash() or t.get("npts") != npts:
+        return None
+    return t.get("bytes_per_launch", {}).get(kernel)
+
+
+def cpu_baseline(w, psi0, seconds: float):
+    import oracle
+    cfg = oracle.Cfg(dim=2, nx=w.nx, ny=w.ny, dx=w.dx, dy=w.dy, c0=w.c0, c2=w.c2, gamma=w.gamma,
+                     omega=w.omega, dt=w.dt, imag=False, so=w.so)
+    psi = psi0
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds and steps < 400:
+        psi = oracle.step(cfg, psi, 2)
+        steps += 2
+    el = time.perf_counter() - t0
+    return {"value": w.nx * w.ny * steps / el, "unit": "grid-point-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {steps} steps of the 1024^2 real-time workload from its initial state "
+                      f"({el:.1f} s, FP64, OpenMP over grid lines)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--obs-every", type=int, default=100)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--profile-every", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run torch copies of the state size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the stepper has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2009_13507_amd import api
+    from paper_2009_13507_amd import workloads as W
+
+    w = W.W2D_REAL
+    psi0 = W.initial_2d_real(w)
+    dev = torch.device("cuda:0")
+    tdtype = torch.complex128 if args.dtype == "f64" else torch.complex64
+    init = torch.from_numpy(psi0).to(dev).to(tdtype)
+    state = init.clone()
+    g = api.Grid(state, w.dx, w.dy)
+    g.set_params(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, dt=w.dt, so=w.so)
+
+    # warm-up on the same buffers, then restart from the initial state
+    g.step_real(args.warmup)
+    g.observables()
+    state.copy_(init)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    obs_log = []
+    g.profile(args.profile_every, capacity=K // max(1, args.profile_every) + 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obs_log.append(g.observables())
+    done = 0
+    while done < K:
+        n = min(args.obs_every, K - done)
+        g.step_real(n)
+        done += n
+        obs_log.append(g.observables())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = g.profile_read()
+    g.profile(0)
+
+    npts = w.nx * w.ny
+    value = npts * K / el
+    bpp = BYTES_PER_PT_PASS[args.dtype]
+    per_launch = bpp * npts
+    kern = "xpass" if prof["x_ms"] >= prof["y_ms"] else "ypass"
+    mean_ms = max(prof["x_ms"], prof["y_ms"])
+    achieved = per_launch / (mean_ms * 1e-3) / 1e9
+    traffic = measured_traffic(kern, npts)
+
+    if args.copy_probe:
+        a = init.clone()
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    line = {
+        "metric": "2D SS-CN grid-point-steps/s, 1024^2 FP64, % of HBM peak; fwd+adjoint cost ratio",
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "dx": w.dx, "dt": w.dt,
+                   "c0": w.c0, "c2": w.c2, "gamma": w.gamma, "so": "gamma p_x Sigma_x",
+                   "omega": w.omega, "observables_every": args.obs_every,
+                   "initial_state": "256^2 imaginary-time ground state, linearly interpolated"},
+        "hbm_frac_step_algorithmic": 2 * bpp * value / (HBM_PEAK_GBS * 1e9),
+        "kernels_ms": {"xpass": prof["x_ms"], "ypass": prof["y_ms"], "profiled_steps": prof["steps"]},
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": per_launch},
+        "final_observables": {k: obs_log[-1][k] for k in ("N", "M", "E", "rms")},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, psi0, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

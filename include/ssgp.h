@@ -99,8 +99,9 @@ typedef struct {
 /* Creates a grid bound to the caller's state buffer psi_dev (3*ny*nx complex
  * elements of dtype, device memory, must outlive the grid) and stream
  * hip_stream (a hipStream_t, or NULL for the default stream).
- * dim = 1 (ny must be 1) or 2.  nx, ny >= 1; ny <= 2048; nx <= 2048 (C128) or 4096
- * (C64) since one row of all three components is staged in LDS.
+ * dim = 1 (ny must be 1) or 2.  1 <= nx, ny <= 2048 (one row of all three
+ * components is staged in LDS, and a line is solved by one wavefront of 64
+ * lanes with chunks of at most 32 points).
  * dx > 0, dy > 0 (dy ignored in 1D).  On success *out owns the workspace. */
 int ssgp_create_grid(int dim, int nx, int ny, double dx, double dy, int dtype,
                      void *psi_dev, void *hip_stream, ssgp_grid *out);
@@ -180,6 +181,15 @@ int ssgp_batch_step_imag_serial(ssgp_batch b, int nsteps);
 int ssgp_batch_observables(ssgp_batch b, ssgp_obs *out);
 
 int ssgp_destroy_batch(ssgp_batch b);
+
+/* Kernel timing for measurement: with every > 0, HIP events are recorded on
+ * the grid's stream around the x-pass and the y-pass of every every-th 2D
+ * step, for at most capacity steps (every = 0 turns it off and frees the
+ * events).  ssgp_profile_read synchronises the stream and writes
+ * out[0..4] = {profiled steps, mean x-pass ms, mean y-pass ms, min x-pass ms,
+ * min y-pass ms}, then restarts the count. */
+int ssgp_profile(ssgp_grid g, int every, int capacity);
+int ssgp_profile_read(ssgp_grid g, double *out);
 
 /* Message of the calling thread's last error ("" if none). */
 const char *ssgp_last_error(void);

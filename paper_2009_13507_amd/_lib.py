@@ -81,6 +81,8 @@ def load():
         "ssgp_batch_step_imag_serial": ([G, ci], ci),
         "ssgp_batch_observables": ([G, ctypes.POINTER(Obs)], ci),
         "ssgp_destroy_batch": ([G], ci),
+        "ssgp_profile": ([G, ci, ci], ci),
+        "ssgp_profile_read": ([G, ctypes.POINTER(cd)], ci),
         "ssgp_last_error": ([], ctypes.c_char_p),
         "ssgp_version": ([], ctypes.c_char_p),
     }

@@ -130,6 +130,15 @@ class Grid:
         check(self._lib.ssgp_omega_grad(self._h, out, self.nseg, 1 if reset else 0))
         return [out[i] for i in range(self.nseg)]
 
+    def profile(self, every: int, capacity: int = 4096):
+        """Records HIP events around the x- and y-pass of every every-th step."""
+        check(self._lib.ssgp_profile(self._h, int(every), int(capacity)))
+
+    def profile_read(self) -> dict:
+        out = (ctypes.c_double * 5)()
+        check(self._lib.ssgp_profile_read(self._h, out))
+        return {"steps": int(out[0]), "x_ms": out[1], "y_ms": out[2], "x_ms_min": out[3], "y_ms_min": out[4]}
+
     def observables(self) -> dict:
         o = Obs()
         rc = self._lib.ssgp_observables(self._h, ctypes.byref(o))

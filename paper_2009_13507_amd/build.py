@@ -1,27 +1,50 @@
-"""Builds libssgp.so for gfx950 with hipcc (in-tree, next to this file)."""
+"""Builds libssgp.so for gfx950 with hipcc (in-tree, next to this file).
+
+The kernels are split over translation units (one per kernel family and
+state precision) that compile in parallel and link into one shared library.
+"""
 from __future__ import annotations
 
+import concurrent.futures as cf
+import glob
 import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "ssgp.hip")
+CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libssgp.so")
+OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions in any generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, SRC]
-    res = subprocess.run(cmd, capture_output=True, text=True)
+def sources():
+    return [os.path.join(CSRC, "ssgp.hip")] + sorted(glob.glob(os.path.join(CSRC, "tu_*.hip")))
+
+
+def _compile(hipcc: str, src: str) -> str:
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    res = subprocess.run([hipcc, *HIPCC_FLAGS, "-c", "-o", obj, src], capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stderr[-4000:])
+        raise RuntimeError(f"hipcc failed on {os.path.basename(src)}:\n" + res.stderr[-4000:])
+    return obj
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(hipcc, s), sources()))
+    tmp = OUT + ".tmp"
+    res = subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs],
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("link failed:\n" + res.stderr[-4000:])
     if verbose:
         print(res.stderr)
     os.replace(tmp, OUT)

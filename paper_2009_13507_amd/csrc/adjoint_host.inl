@@ -1,30 +1,5 @@
 // adjoint_host.inl -- host side of the real-time adjoint (included by ssgp.hip).
 
-template <typename R, int L>
-static int launch_adj_x_L(const GridCore &g, const AdjXArgs<R> &a) {
-    const size_t lds = (size_t)3 * srow<L>(g.nx) * sizeof(cx<R>);
-    if (lds > 64 * 1024)
-        HIP_TRY(hipFuncSetAttribute((const void *)adj_xpass_kernel<R, L>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const int rows = g.dim == 2 ? g.ny : 1;
-    adj_xpass_kernel<R, L><<<rows, XPASS_THREADS, lds, g.stream>>>(a);
-    HIP_TRY(hipGetLastError());
-    return SSGP_OK;
-}
-
-template <typename R> static int launch_adj_x(const GridCore &g, const AdjXArgs<R> &a, int L) {
-    switch (L) {
-    case 1: return launch_adj_x_L<R, 1>(g, a);
-    case 2: return launch_adj_x_L<R, 2>(g, a);
-    case 4: return launch_adj_x_L<R, 4>(g, a);
-    case 8: return launch_adj_x_L<R, 8>(g, a);
-    case 16: return launch_adj_x_L<R, 16>(g, a);
-    case 32: return launch_adj_x_L<R, 32>(g, a);
-    case 64: return launch_adj_x_L<R, 64>(g, a);
-    default: return fail(SSGP_EINVAL, "unsupported x chunk %d", L);
-    }
-}
-
 template <typename R>
 static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps) {
     if (so_has_y(g->p.so) && g->p.gamma != 0.0)
@@ -60,9 +35,7 @@ static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps)
         a.x0 = (R)(-0.5 * g->nx * g->dx);
         a.y0 = (R)(g->dim == 2 ? -0.5 * g->ny * g->dy : 0.0);
         a.m = model<R>(*g, MODE_REAL, omega);
-        a.inv = T.x[MODE_ADJ].inv();
-        a.cp = T.x[MODE_ADJ].cp();
-        a.chunkA = T.x[MODE_ADJ].chunkA();
+        a.cx_ = T.x[MODE_ADJ].coef();
         a.rdiag = T.x[MODE_ADJ].rdiag;
         a.roff = T.x[MODE_ADJ].roff;
         XArgs<R> tmp{};
@@ -70,10 +43,9 @@ static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps)
         for (int q = 0; q < 9; ++q) a.qx[q] = tmp.qx[q];
         a.qxmask = tmp.qxmask;
         a.omega_partials = g->adj_partials.as<double>();
-        SSGP_TRY(launch_adj_x<R>(*g, a, Lx));
-        omega_accumulate_kernel<<<1, 256, 0, g->stream>>>(g->adj_partials.as<double>(), rows,
-                                                          g->omega_acc.as<double>(), seg);
-        HIP_TRY(hipGetLastError());
+        LAUNCH_TRY(launch_adj_xpass<R>(lc(*g), a, Lx, rows));
+        LAUNCH_TRY(launch_omega_accumulate(lc(*g), g->adj_partials.as<double>(), rows, g->omega_acc.as<double>(),
+                                           seg));
     }
     g->step_index = n0;
     return SSGP_OK;

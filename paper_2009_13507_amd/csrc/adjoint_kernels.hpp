@@ -152,15 +152,15 @@ template <typename R> struct AdjXArgs {
     long long plane;
     R dx, dy, x0, y0;
     Model<R> m;
-    const cx<R> *inv, *cp, *chunkA;  // CN_x tables with the conjugate factor
+    LineCoef<R> cx_;           // CN_x coefficients with the conjugate factor
     cx<R> rdiag, roff;
     cx<R> qx[9];               // SO^H stencil couplings
     unsigned qxmask;
     double *omega_partials;    // [ny] per-row Omega derivative
 };
 
-template <typename R, int L>
-__global__ void __launch_bounds__(XPASS_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
+template <typename R, int L, bool GENERAL>
+__global__ void __launch_bounds__(ROW_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
     extern __shared__ unsigned char smem_raw[];
     cx<R> *s = reinterpret_cast<cx<R> *>(smem_raw);
     __shared__ double red[3];
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) adj_xpass_kernel(AdjXArgs<R> a)
     cx<R> *lam = a.lam + roff;
     const cx<R> *psi = a.psi_n + roff;
 
-    for (int i = tid; i < nx; i += XPASS_THREADS) {
+    for (int i = tid; i < nx; i += ROW_THREADS) {
         const int si = sidx<L>(i);
         s[si] = lam[i];
         s[ld + si] = lam[a.plane + i];
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) adj_xpass_kernel(AdjXArgs<R> a)
                 r[t] = czero<R>();
             }
         }
-        solve_line_wave<R, L>(r, start, len, a.inv, a.cp, a.chunkA[lane]);
+        solve_line_wave<R, L, GENERAL>(r, start, len, a.cx_);
 #pragma unroll
         for (int t = 0; t < L; ++t)
             if (t < len) sj[sidx<L>(start + t)] = r[t];
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) adj_xpass_kernel(AdjXArgs<R> a)
     const R yv = a.y0 + R(row) * a.dy;
     const R vy = R(0.5) * a.m.kappa2 * yv * yv;
     double dom = 0.0;
-    for (int i = tid; i < nx; i += XPASS_THREADS) {
+    for (int i = tid; i < nx; i += ROW_THREADS) {
         cx<R> g[3], p[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -239,22 +239,6 @@ __global__ void __launch_bounds__(XPASS_THREADS) adj_xpass_kernel(AdjXArgs<R> a)
     if ((tid & 63) == 0) red[tid >> 6] = dom;
     __syncthreads();
     if (tid == 0) a.omega_partials[row] = red[0] + red[1] + red[2];
-}
-
-// Adds the per-row Omega derivatives of one adjoint step (fixed order) to
-// acc[seg].
-__global__ void __launch_bounds__(256) omega_accumulate_kernel(const double *partials, int nrows, double *acc,
-                                                               int seg) {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int q = threadIdx.x; q < nrows; q += 256) s += partials[q];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) acc[seg] += red[0];
 }
 
 } // namespace ssgp

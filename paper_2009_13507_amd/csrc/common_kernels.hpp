@@ -1,0 +1,72 @@
+// common_kernels.hpp -- the small single-workgroup reduction kernels
+// (fixed-order sums, run-to-run reproducible).  Included by one translation
+// unit only.
+#pragma once
+#include "adjoint_kernels.hpp"
+#include "obs_kernels.hpp"
+#include "step_kernels.hpp"
+
+namespace ssgp {
+
+// Sums the per-tile |psi|^2 partials (fixed order) and writes
+// out = {d_+1, d_0, d_-1, N_+1, N_0, N_-1, fallback}.
+__global__ void __launch_bounds__(256) renorm_finalize_kernel(const double *partials, int ntiles,
+                                                              RenormSpec sp, double *out) {
+    __shared__ double red[3][256];
+    const int t = threadIdx.x;
+    for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int q = t; q < ntiles; q += 256) s += partials[(long long)j * ntiles + q];
+        red[j][t] = s;
+    }
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w)
+            for (int j = 0; j < 3; ++j) red[j][t] += red[j][t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double N[3] = {red[0][0] * sp.dA, red[1][0] * sp.dA, red[2][0] * sp.dA};
+        double d[3], fb = 0.0;
+        renorm_factors(sp, N, d, &fb);
+        for (int j = 0; j < 3; ++j) {
+            out[j] = d[j];
+            out[3 + j] = N[j];
+        }
+        out[6] = fb;
+    }
+}
+
+__global__ void __launch_bounds__(256) obs_finalize_kernel(const double *partials, int nblocks, double *out) {
+    __shared__ double red[256];
+    for (int q = 0; q < OBS_NQ; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(long long)b * OBS_NQ + q];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[q] = red[0];
+        __syncthreads();
+    }
+}
+
+// Adds the per-row Omega derivatives of one adjoint step (fixed order) to
+// acc[seg].
+__global__ void __launch_bounds__(256) omega_accumulate_kernel(const double *partials, int nrows, double *acc,
+                                                               int seg) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nrows; q += 256) s += partials[q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[seg] += red[0];
+}
+
+} // namespace ssgp

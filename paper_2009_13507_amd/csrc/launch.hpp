@@ -1,0 +1,51 @@
+// launch.hpp -- host launchers of the kernels, one translation unit per
+// kernel family and state precision (compiled in parallel).  Each returns
+// hipSuccess or the HIP error of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "adjoint_kernels.hpp"
+#include "obs_kernels.hpp"
+#include "step_kernels.hpp"
+
+namespace ssgp {
+
+struct Launch {
+    hipStream_t stream;
+    int ncu;  // compute units of the device
+};
+
+// Dynamic LDS of the x-pass: one staged line (one padding slot per chunk)
+// and the edge exchange area.
+template <typename R> inline size_t xpass_lds(int nx, int L) {
+    return ((size_t)(nx + nx / L + 1) + 48) * sizeof(cx<R>);
+}
+// Dynamic LDS of the 1D and adjoint row kernels: all three components.
+template <typename R> inline size_t row_lds(int nx, int L) { return (size_t)3 * (nx + nx / L + 1) * sizeof(cx<R>); }
+
+template <typename R> hipError_t launch_xpass(const Launch &c, const XArgs<R> &a, int L, int rows);
+template <typename R> hipError_t launch_ypass(const Launch &c, const YArgs<R> &a, int L, int tx, int threads);
+template <typename R> hipError_t launch_step1d(const Launch &c, const Args1D<R> &a, int L);
+template <typename R> hipError_t launch_adj_xpass(const Launch &c, const AdjXArgs<R> &a, int L, int rows);
+template <typename R> hipError_t launch_pointwise(const Launch &c, const PArgs<R> &a, int blocks);
+template <typename R> hipError_t launch_scale(const Launch &c, cx<R> *psi, long long plane, const double *d, int blocks);
+template <typename R> hipError_t launch_obs(const Launch &c, const ObsArgs<R> &a, int blocks);
+hipError_t launch_renorm_finalize(const Launch &c, const double *partials, int ntiles, RenormSpec sp, double *out);
+hipError_t launch_obs_finalize(const Launch &c, const double *partials, int nblocks, double *out);
+hipError_t launch_omega_accumulate(const Launch &c, const double *partials, int nrows, double *acc, int seg);
+
+// chunk lengths with compiled kernels (row kernels: one 64-lane wavefront
+// per line, so nx <= 64 L <= 2048)
+#define SSGP_SWITCH_L(L, GEN, CALL)                                                                   \
+    switch (L) {                                                                                      \
+    case 1: return CALL(1, true);                                                                     \
+    case 2: return CALL(2, true);                                                                     \
+    case 4: return CALL(4, true);                                                                     \
+    case 8: return GEN ? CALL(8, true) : CALL(8, false);                                              \
+    case 16: return GEN ? CALL(16, true) : CALL(16, false);                                           \
+    case 32: return GEN ? CALL(32, true) : CALL(32, false);                                           \
+    default: return hipErrorInvalidValue;                                                             \
+    }
+
+
+} // namespace ssgp

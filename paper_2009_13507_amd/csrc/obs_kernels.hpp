@@ -111,20 +111,4 @@ __global__ void __launch_bounds__(256) obs_kernel(ObsArgs<R> a) {
     }
 }
 
-__global__ void __launch_bounds__(256) obs_finalize_kernel(const double *partials, int nblocks, double *out) {
-    __shared__ double red[256];
-    for (int q = 0; q < OBS_NQ; ++q) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(long long)b * OBS_NQ + q];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w >= 1; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[q] = red[0];
-        __syncthreads();
-    }
-}
-
 } // namespace ssgp

@@ -18,10 +18,7 @@
 #include <vector>
 
 #include "../../include/ssgp.h"
-#include "adjoint_kernels.hpp"
-#include "batch_kernels.hpp"
-#include "obs_kernels.hpp"
-#include "step_kernels.hpp"
+#include "launch.hpp"
 
 using namespace ssgp;
 using cd = std::complex<double>;
@@ -44,6 +41,12 @@ static int fail(int code, const char *fmt, ...) {
         hipError_t e_ = (expr);                                                              \
         if (e_ != hipSuccess)                                                                \
             return fail(SSGP_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+#define LAUNCH_TRY(expr)                                                                     \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(SSGP_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
     } while (0)
 
 #define SSGP_TRY(expr)                                                                       \
@@ -77,58 +80,79 @@ struct DevBuf {
 // ------------------------------------------------- CN coefficient tables -
 // (I + sT) with T = tridiag(-1/(2h^2), 1/h^2, -1/(2h^2)): diagonal
 // d = 1 + s/h^2, off-diagonal o = -s/(2h^2).  Thomas pivots m_0 = d,
-// m_i = d - o c'_{i-1}; inv_i = 1/m_i, c'_i = o inv_i.  Chunk products
-// A_k = prod_{i in chunk k} (-c'_i) (1 for empty chunks).
+// m_i = d - o c'_{i-1}, c'_i = o / m_i.  The kernels use y_i = c'_i (r_i/o -
+// y_{i-1}), so the right-hand side (I - sT) u is built divided by o.  Chunk
+// products A_k = prod_{i in chunk k} (-c'_i) (1 for empty chunks).
 struct CNHost {
-    std::vector<cd> inv, cp, chunkA;
-    cd rdiag, roff;
+    std::vector<cd> cp, chunkA;
+    cd rdiag, roff;  // (I - sT) / o: diagonal and off-diagonal
+    int levels;      // scan levels needed for carries above 2^-64
 };
 
-static CNHost cn_tables(int n, double h, cd s, int L, int nchunks) {
+static CNHost cn_tables(int n, double h, cd s, int L, int nchunks, int max_levels) {
     CNHost t;
     const cd d = 1.0 + s / (h * h), o = -s / (2.0 * h * h);
-    t.inv.resize(n);
     t.cp.resize(n);
-    t.inv[0] = 1.0 / d;
-    t.cp[0] = o * t.inv[0];
-    for (int i = 1; i < n; ++i) {
-        const cd m = d - o * t.cp[i - 1];
-        t.inv[i] = 1.0 / m;
-        t.cp[i] = o * t.inv[i];
-    }
+    t.cp[0] = o / d;
+    for (int i = 1; i < n; ++i) t.cp[i] = o / (d - o * t.cp[i - 1]);
     t.chunkA.assign(nchunks, cd(1.0, 0.0));
-    for (int k = 0; k < nchunks; ++k)
+    double amax = 0.0;
+    for (int k = 0; k < nchunks; ++k) {
         for (int i = k * L; i < std::min(n, (k + 1) * L); ++i) t.chunkA[k] *= -t.cp[i];
-    t.rdiag = 1.0 - s / (h * h);
-    t.roff = s / (2.0 * h * h);
+        if (k * L < n) amax = std::max(amax, std::abs(t.chunkA[k]));
+    }
+    t.rdiag = (1.0 - s / (h * h)) / o;
+    t.roff = (s / (2.0 * h * h)) / o;
+    // A carry from W+1 or more chunks back is scaled by at most amax^(W+1);
+    // take the smallest W = 2^levels - 1 with amax^(W+1) <= 2^-64.
+    int levels = max_levels;
+    if (amax < 1.0) {
+        const double need = amax > 0.0 ? 64.0 * std::log(2.0) / -std::log(amax) : 1.0;
+        levels = 1;
+        while (levels < max_levels && (double)(1 << levels) < need) ++levels;
+    }
+    t.levels = levels;
     return t;
 }
 
 template <typename R> struct CNDev {
-    DevBuf buf;  // inv[n] | cp[n] | chunkA[nchunks]
-    int n = 0, L = 0, nchunks = 0;
-    cx<R> rdiag{}, roff{};
-    const cx<R> *inv() const { return buf.as<cx<R>>(); }
-    const cx<R> *cp() const { return buf.as<cx<R>>() + n; }
-    const cx<R> *chunkA() const { return buf.as<cx<R>>() + 2 * n; }
+    DevBuf buf;  // cp[n] | chunkA[nchunks]
+    int n = 0, L = 0, nchunks = 0, head = 1, levels = 6;
+    cx<R> rdiag{}, roff{}, cp_inf{};
+    const cx<R> *cp() const { return buf.as<cx<R>>(); }
+    const cx<R> *chunkA() const { return buf.as<cx<R>>() + n; }
+    LineCoef<R> coef() const {
+        LineCoef<R> c;
+        c.cp = cp();
+        c.chunkA = chunkA();
+        c.cp_inf = cp_inf;
+        c.head = head;
+        c.levels = levels;
+        return c;
+    }
 };
 
 template <typename R> static cx<R> tor(cd v) { return cx<R>{(R)v.real(), (R)v.imag()}; }
+template <typename R> static bool same(cx<R> a, cx<R> b) { return a.x == b.x && a.y == b.y; }
 
 template <typename R>
 static int upload_cn(CNDev<R> &dst, const CNHost &h, int n, int L, int nchunks, hipStream_t st) {
-    std::vector<cx<R>> host(2 * n + nchunks);
-    for (int i = 0; i < n; ++i) {
-        host[i] = tor<R>(h.inv[i]);
-        host[n + i] = tor<R>(h.cp[i]);
-    }
-    for (int k = 0; k < nchunks; ++k) host[2 * n + k] = tor<R>(h.chunkA[k]);
+    std::vector<cx<R>> host(n + nchunks);
+    for (int i = 0; i < n; ++i) host[i] = tor<R>(h.cp[i]);
+    for (int k = 0; k < nchunks; ++k) host[n + k] = tor<R>(h.chunkA[k]);
+    // the pivots become stationary in the table precision: entries from
+    // index head on all equal the last one
+    int head = n - 1;
+    while (head >= 1 && same(host[head - 1], host[n - 1])) --head;
     SSGP_TRY(dst.buf.ensure(host.size() * sizeof(cx<R>)));
     HIP_TRY(hipMemcpyAsync(dst.buf.p, host.data(), host.size() * sizeof(cx<R>), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     dst.n = n;
     dst.L = L;
     dst.nchunks = nchunks;
+    dst.head = std::max(head, 1);
+    dst.levels = h.levels;
+    dst.cp_inf = host[n - 1];
     dst.rdiag = tor<R>(h.rdiag);
     dst.roff = tor<R>(h.roff);
     return SSGP_OK;
@@ -143,13 +167,13 @@ static int pow2_at_least(int v) {
 // chunk length of an x line handled by one 64-lane wavefront
 static int x_chunk(int nx) { return pow2_at_least((nx + 63) / 64); }
 
-// y-pass shape: TX columns per workgroup, chunks of LY rows, P chunks.
+// y-pass shape: TX columns per workgroup, chunks of L rows, P chunks.
 constexpr int YTX = 8;
 struct YShape {
     int L, P, threads;
 };
 static YShape y_shape(int ny) {
-    // smallest chunk (8, 16 or 32 rows) that fits the column in 512 lanes
+    // smallest chunk (8, 16 or 32 rows) with at most 512 lanes per column tile
     int L = 8;
     while (L < 32 && YTX * ((ny + L - 1) / L) > YPASS_MAX_THREADS) L <<= 1;
     int P = (ny + L - 1) / L;
@@ -222,6 +246,7 @@ enum { MODE_REAL = 0, MODE_IMAG = 1, MODE_ADJ = 2, NMODES = 3 };
 
 struct GridCore {
     int dim = 2, nx = 0, ny = 1;
+    int ncu = 1;  // compute units of the device
     double dx = 0, dy = 0;
     int dtype = SSGP_C128;
     void *psi = nullptr;
@@ -233,6 +258,14 @@ struct GridCore {
     long long step_index = 0;
     DevBuf partials, renorm, obs_partials, obs_out, scratch, omega_acc, adj_partials;
     int built_mode_mask = 0;
+    // kernel timing: events around the x-pass and y-pass of every
+    // prof_every-th step (event pairs [x0, x1, y0, y1] per profiled step)
+    int prof_every = 0, prof_cap = 0, prof_used = 0;
+    long long prof_counter = 0;
+    std::vector<hipEvent_t> prof_events;
+    ~GridCore() {
+        for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
+    }
 };
 
 template <typename R> struct Tables {
@@ -265,10 +298,13 @@ template <typename R> static int build_tables(ssgp_grid g, int mode) {
     Tables<R> &T = tables<R>(g);
     const cd s = cn_s(mode, g->p.dt);
     const int Lx = x_chunk(g->nx);
-    SSGP_TRY(upload_cn<R>(T.x[mode], cn_tables(g->nx, g->dx, s, Lx, 64), g->nx, Lx, 64, g->stream));
+    SSGP_TRY(upload_cn<R>(T.x[mode], cn_tables(g->nx, g->dx, s, Lx, 64, 6), g->nx, Lx, 64, g->stream));
     if (g->dim == 2) {
         const YShape ys = y_shape(g->ny);
-        SSGP_TRY(upload_cn<R>(T.y[mode], cn_tables(g->ny, g->dy, s, ys.L, ys.P), g->ny, ys.L, ys.P, g->stream));
+        int maxlv = 0;
+        while ((YTX << maxlv) < 64) ++maxlv;
+        SSGP_TRY(upload_cn<R>(T.y[mode], cn_tables(g->ny, g->dy, s, ys.L, ys.P, maxlv), g->ny, ys.L, ys.P,
+                              g->stream));
     }
     g->built_mode_mask |= 1 << mode;
     return SSGP_OK;
@@ -303,48 +339,17 @@ template <typename R> static Model<R> model(const GridCore &g, int mode, double 
 }
 
 // ------------------------------------------------------------ launches --
-template <typename R, int L>
-static int launch_x_L(const GridCore &g, const XArgs<R> &a) {
-    const int ld = srow<L>(g.nx);
-    const size_t lds = (size_t)(a.so_y ? 6 : 3) * ld * sizeof(cx<R>);
-    if (lds > 160 * 1024) return fail(SSGP_EINVAL, "row of nx=%d does not fit in LDS", g.nx);
-    if (lds > 64 * 1024)
-        HIP_TRY(hipFuncSetAttribute((const void *)xpass_kernel<R, L>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const int rows = g.dim == 2 ? g.ny : 1;
-    xpass_kernel<R, L><<<rows, XPASS_THREADS, lds, g.stream>>>(a);
-    HIP_TRY(hipGetLastError());
-    return SSGP_OK;
-}
+static Launch lc(const GridCore &g) { return Launch{g.stream, g.ncu}; }
 
 template <typename R> static int launch_x(const GridCore &g, const XArgs<R> &a, int L) {
-    switch (L) {
-    case 1: return launch_x_L<R, 1>(g, a);
-    case 2: return launch_x_L<R, 2>(g, a);
-    case 4: return launch_x_L<R, 4>(g, a);
-    case 8: return launch_x_L<R, 8>(g, a);
-    case 16: return launch_x_L<R, 16>(g, a);
-    case 32: return launch_x_L<R, 32>(g, a);
-    case 64: return launch_x_L<R, 64>(g, a);
-    default: return fail(SSGP_EINVAL, "unsupported x chunk %d", L);
-    }
-}
-
-template <typename R, int L>
-static int launch_y_L(const GridCore &g, const YArgs<R> &a, const YShape &ys) {
-    dim3 grid((g.nx + YTX - 1) / YTX, 3);
-    ypass_kernel<R, L, YTX><<<grid, ys.threads, 0, g.stream>>>(a);
-    HIP_TRY(hipGetLastError());
+    if (xpass_lds<R>(g.nx, L) > 160 * 1024) return fail(SSGP_EINVAL, "a row of nx=%d does not fit in LDS", g.nx);
+    LAUNCH_TRY(launch_xpass<R>(lc(g), a, L, g.dim == 2 ? g.ny : 1));
     return SSGP_OK;
 }
 
 template <typename R> static int launch_y(const GridCore &g, const YArgs<R> &a, const YShape &ys) {
-    switch (ys.L) {
-    case 8: return launch_y_L<R, 8>(g, a, ys);
-    case 16: return launch_y_L<R, 16>(g, a, ys);
-    case 32: return launch_y_L<R, 32>(g, a, ys);
-    default: return fail(SSGP_EINVAL, "unsupported y chunk %d", ys.L);
-    }
+    LAUNCH_TRY(launch_ypass<R>(lc(g), a, ys.L, YTX, ys.threads));
+    return SSGP_OK;
 }
 
 template <typename R>
@@ -378,9 +383,7 @@ static XArgs<R> x_args(ssgp_grid g, int mode, const void *src, void *dst, double
     a.m = model<R>(*g, mode, omega);
     a.dscale = dscale;
     a.pointwise = 1;
-    a.inv = T.x[mode].inv();
-    a.cp = T.x[mode].cp();
-    a.chunkA = T.x[mode].chunkA();
+    a.cx_ = T.x[mode].coef();
     a.rdiag = T.x[mode].rdiag;
     a.roff = T.x[mode].roff;
     fill_so(a, *g, mode);
@@ -396,9 +399,7 @@ static YArgs<R> y_args(ssgp_grid g, int mode, void *psi, double *partials) {
     a.nx = g->nx;
     a.ny = g->ny;
     a.plane = plane_of(*g);
-    a.inv = T.y[mode].inv();
-    a.cp = T.y[mode].cp();
-    a.chunkA = T.y[mode].chunkA();
+    a.cy = T.y[mode].coef();
     a.rdiag = T.y[mode].rdiag;
     a.roff = T.y[mode].roff;
     a.norm_partials = partials;
@@ -424,6 +425,10 @@ static int ew_blocks(long long n) { return (int)std::min<long long>((n + 255) / 
 template <typename R>
 static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omega, const double *dscale) {
     const bool imag = mode == MODE_IMAG;
+    hipEvent_t *ev = nullptr;
+    if (g->prof_every > 0 && (g->prof_counter++ % g->prof_every) == 0 && g->prof_used < g->prof_cap)
+        ev = &g->prof_events[(size_t)4 * g->prof_used++];
+    if (ev) HIP_TRY(hipEventRecord(ev[0], g->stream));
     const int Lx = x_chunk(g->nx);
     const YShape ys = y_shape(g->ny);
     const int ntiles = (g->nx + YTX - 1) / YTX;
@@ -444,8 +449,7 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
         pa.y0 = (R)(-0.5 * g->ny * g->dy);
         pa.m = model<R>(*g, mode, omega);
         pa.dscale = dscale;
-        pointwise_kernel<R><<<ew_blocks(pa.plane), 256, 0, g->stream>>>(pa);
-        HIP_TRY(hipGetLastError());
+        LAUNCH_TRY(launch_pointwise<R>(lc(*g), pa, ew_blocks(pa.plane)));
         XArgs<R> xa = x_args<R>(g, mode, g->scratch.p, dst, omega, nullptr);
         xa.pointwise = 0;
         xa.so_y = 1;
@@ -454,18 +458,21 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
         XArgs<R> xa = x_args<R>(g, mode, src, dst, omega, dscale);
         SSGP_TRY(launch_x<R>(*g, xa, Lx));
     }
+    if (ev) {
+        HIP_TRY(hipEventRecord(ev[1], g->stream));
+        HIP_TRY(hipEventRecord(ev[2], g->stream));
+    }
     YArgs<R> ya = y_args<R>(g, mode, dst, imag ? g->partials.as<double>() : nullptr);
     SSGP_TRY(launch_y<R>(*g, ya, ys));
+    if (ev) HIP_TRY(hipEventRecord(ev[3], g->stream));
     if (imag) {
-        renorm_finalize_kernel<<<1, 256, 0, g->stream>>>(g->partials.as<double>(), ntiles, renorm_spec(*g),
-                                                         g->renorm.as<double>());
-        HIP_TRY(hipGetLastError());
+        LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), ntiles, renorm_spec(*g),
+                                          g->renorm.as<double>()));
     }
     return SSGP_OK;
 }
 
-template <typename R, int L>
-static int launch_1d_L(ssgp_grid g, int mode, void *psi, int nsteps, double omega) {
+template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int nsteps, double omega) {
     Tables<R> &T = tables<R>(g);
     Args1D<R> a{};
     a.psi = static_cast<cx<R> *>(psi);
@@ -474,9 +481,7 @@ static int launch_1d_L(ssgp_grid g, int mode, void *psi, int nsteps, double omeg
     a.dx = (R)g->dx;
     a.x0 = (R)(-0.5 * g->nx * g->dx);
     a.m = model<R>(*g, mode, omega);
-    a.inv = T.x[mode].inv();
-    a.cp = T.x[mode].cp();
-    a.chunkA = T.x[mode].chunkA();
+    a.cx_ = T.x[mode].coef();
     a.rdiag = T.x[mode].rdiag;
     a.roff = T.x[mode].roff;
     XArgs<R> tmp{};
@@ -485,26 +490,8 @@ static int launch_1d_L(ssgp_grid g, int mode, void *psi, int nsteps, double omeg
     a.qxmask = tmp.qxmask;
     a.sp = renorm_spec(*g);
     a.renorm_out = g->renorm.as<double>();
-    const size_t lds = (size_t)3 * srow<L>(g->nx) * sizeof(cx<R>);
-    if (lds > 64 * 1024)
-        HIP_TRY(hipFuncSetAttribute((const void *)step1d_kernel<R, L>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    step1d_kernel<R, L><<<1, XPASS_THREADS, lds, g->stream>>>(a);
-    HIP_TRY(hipGetLastError());
+    LAUNCH_TRY(launch_step1d<R>(lc(*g), a, x_chunk(g->nx)));
     return SSGP_OK;
-}
-
-template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int nsteps, double omega) {
-    switch (x_chunk(g->nx)) {
-    case 1: return launch_1d_L<R, 1>(g, mode, psi, nsteps, omega);
-    case 2: return launch_1d_L<R, 2>(g, mode, psi, nsteps, omega);
-    case 4: return launch_1d_L<R, 4>(g, mode, psi, nsteps, omega);
-    case 8: return launch_1d_L<R, 8>(g, mode, psi, nsteps, omega);
-    case 16: return launch_1d_L<R, 16>(g, mode, psi, nsteps, omega);
-    case 32: return launch_1d_L<R, 32>(g, mode, psi, nsteps, omega);
-    case 64: return launch_1d_L<R, 64>(g, mode, psi, nsteps, omega);
-    default: return fail(SSGP_EINVAL, "unsupported 1D chunk");
-    }
 }
 
 template <typename R> static int step_imag_t(ssgp_grid g, int nsteps) {
@@ -513,9 +500,8 @@ template <typename R> static int step_imag_t(ssgp_grid g, int nsteps) {
     for (int s = 0; s < nsteps; ++s)
         SSGP_TRY(step2d<R>(g, MODE_IMAG, g->psi, g->psi, g->p.omega, s == 0 ? nullptr : g->renorm.as<double>()));
     if (nsteps > 0) {
-        scale_kernel<R><<<ew_blocks(plane_of(*g)), 256, 0, g->stream>>>(static_cast<cx<R> *>(g->psi),
-                                                                        plane_of(*g), g->renorm.as<double>());
-        HIP_TRY(hipGetLastError());
+        LAUNCH_TRY(launch_scale<R>(lc(*g), static_cast<cx<R> *>(g->psi), plane_of(*g), g->renorm.as<double>(),
+                                   ew_blocks(plane_of(*g))));
     }
     return SSGP_OK;
 }
@@ -579,8 +565,7 @@ extern "C" int ssgp_create_grid(int dim, int nx, int ny, double dx, double dy, i
     if (dim != 1 && dim != 2) return fail(SSGP_EINVAL, "dim must be 1 or 2");
     if (dtype != SSGP_C128 && dtype != SSGP_C64) return fail(SSGP_EINVAL, "unknown dtype %d", dtype);
     if (dim == 1) ny = 1;
-    const int nxmax = dtype == SSGP_C128 ? 2048 : 4096;
-    if (nx < 1 || nx > nxmax) return fail(SSGP_EINVAL, "nx must be in [1, %d] (got %d)", nxmax, nx);
+    if (nx < 1 || nx > 2048) return fail(SSGP_EINVAL, "nx must be in [1, 2048] (got %d)", nx);
     if (ny < 1 || ny > 2048) return fail(SSGP_EINVAL, "ny must be in [1, 2048] (got %d)", ny);
     if (!(dx > 0) || !std::isfinite(dx) || (dim == 2 && (!(dy > 0) || !std::isfinite(dy))))
         return fail(SSGP_EINVAL, "grid spacing must be positive");
@@ -595,6 +580,14 @@ extern "C" int ssgp_create_grid(int dim, int nx, int ny, double dx, double dy, i
     g->dtype = dtype;
     g->psi = psi_dev;
     g->stream = static_cast<hipStream_t>(hip_stream);
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&g->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || g->ncu < 1) {
+            delete g;
+            return fail(SSGP_EDEVICE, "cannot query the device");
+        }
+    }
     const int ntiles = (nx + YTX - 1) / YTX;
     int rc = g->partials.ensure(sizeof(double) * 3 * ntiles);
     if (rc == SSGP_OK) rc = g->renorm.ensure(sizeof(double) * 8);
@@ -696,10 +689,8 @@ template <typename R> static int observables_t(ssgp_grid g, const void *psi, ssg
     a.hymask = g->p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hy);
     a.partials = g->obs_partials.as<double>();
     const int nb = (int)std::min<long long>((a.plane + 255) / 256, 1024);
-    obs_kernel<R><<<nb, 256, 0, g->stream>>>(a);
-    HIP_TRY(hipGetLastError());
-    obs_finalize_kernel<<<1, 256, 0, g->stream>>>(g->obs_partials.as<double>(), nb, g->obs_out.as<double>());
-    HIP_TRY(hipGetLastError());
+    LAUNCH_TRY(launch_obs<R>(lc(*g), a, nb));
+    LAUNCH_TRY(launch_obs_finalize(lc(*g), g->obs_partials.as<double>(), nb, g->obs_out.as<double>()));
     double h[OBS_NQ];
     HIP_TRY(hipMemcpyAsync(h, g->obs_out.p, sizeof h, hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
@@ -747,6 +738,46 @@ extern "C" int ssgp_destroy(ssgp_grid g) {
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     else (void)hipDeviceSynchronize();
     delete g;
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_profile(ssgp_grid g, int every, int capacity) {
+    if (!g) return fail(SSGP_EINVAL, "grid is NULL");
+    if (every < 0 || capacity < 0 || (every > 0 && capacity == 0)) return fail(SSGP_EINVAL, "bad profile request");
+    for (hipEvent_t e : g->prof_events) (void)hipEventDestroy(e);
+    g->prof_events.clear();
+    g->prof_every = 0;
+    g->prof_cap = g->prof_used = 0;
+    g->prof_counter = 0;
+    if (every == 0) return SSGP_OK;
+    g->prof_events.resize((size_t)4 * capacity);
+    for (auto &e : g->prof_events) HIP_TRY(hipEventCreate(&e));
+    g->prof_every = every;
+    g->prof_cap = capacity;
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_profile_read(ssgp_grid g, double *out) {
+    if (!g || !out) return fail(SSGP_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    double sx = 0, sy = 0, mx = 1e300, my = 1e300;
+    for (int k = 0; k < g->prof_used; ++k) {
+        float tx = 0, ty = 0;
+        HIP_TRY(hipEventElapsedTime(&tx, g->prof_events[4 * k], g->prof_events[4 * k + 1]));
+        HIP_TRY(hipEventElapsedTime(&ty, g->prof_events[4 * k + 2], g->prof_events[4 * k + 3]));
+        sx += tx;
+        sy += ty;
+        mx = std::min(mx, (double)tx);
+        my = std::min(my, (double)ty);
+    }
+    const int n = g->prof_used;
+    out[0] = n;
+    out[1] = n ? sx / n : 0.0;
+    out[2] = n ? sy / n : 0.0;
+    out[3] = n ? mx : 0.0;
+    out[4] = n ? my : 0.0;
+    g->prof_used = 0;
+    g->prof_counter = 0;
     return SSGP_OK;
 }
 

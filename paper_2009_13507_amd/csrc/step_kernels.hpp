@@ -124,18 +124,65 @@ __device__ __forceinline__ void pointwise(cx<R> &p, cx<R> &z, cx<R> &m, R V, con
 }
 
 // -------------------------------------------------- chunked line solve ---
-// Forward sweep of one chunk with zero carry-in; r holds the right-hand side
-// on entry and the partial y on exit.  Returns the last y (0 if empty).
-template <typename R, int L>
-__device__ __forceinline__ cx<R> fwd_local(cx<R> (&r)[L], int start, int len,
-                                           const cx<R> *__restrict__ inv,
-                                           const cx<R> *__restrict__ cp) {
+// Elimination coefficients of one line direction.  With o the
+// off-diagonal of I + sT and m_i the Thomas pivots, c'_i = o / m_i and the
+// forward sweep y_i = (r_i - o y_{i-1}) / m_i is y_i = c'_i (r_i/o - y_{i-1});
+// the right-hand side is built already divided by o.  The pivots of a
+// constant Toeplitz matrix converge: from index head on, c'_i is bitwise
+// equal to cp_inf (the host finds head by running the recurrence in the
+// table precision), so only the head is tabulated.
+template <typename R> struct LineCoef {
+    const cx<R> *cp;        // first head entries of c'_i
+    const cx<R> *chunkA;    // per-chunk products of -c'_i
+    cx<R> cp_inf;
+    int head;               // >= 1
+    int levels;             // scan levels: carries over more than 2^levels - 1
+                            // chunks are below 2^-64 relative and dropped
+};
+
+// Coefficients of one chunk.  When the tabulated head fits in the first
+// chunk (head <= L, the usual case: the pivots converge within a few
+// points), c'_i is cp_inf for every chunk except the first, whose values are
+// the same for all lines and are read with wave-uniform loads; otherwise
+// (GENERAL) every lane reads its chunk's entries (clamped, unconditional
+// loads) into registers.
+template <typename R, int L, bool GENERAL> struct ChunkCoef;
+
+template <typename R, int L> struct ChunkCoef<R, L, false> {
+    const cx<R> *tab;
+    cx<R> tail;
+    int head;
+    bool first;  // this lane's chunk starts at index 0
+    __device__ __forceinline__ ChunkCoef(const LineCoef<R> &C, int start)
+        : tab(C.cp), tail(C.cp_inf), head(C.head), first(start == 0) {}
+    __device__ __forceinline__ cx<R> operator[](int t) const {
+        const cx<R> h = tab[t < head ? t : head - 1];  // uniform address
+        return (first && t < head) ? h : tail;
+    }
+};
+
+template <typename R, int L> struct ChunkCoef<R, L, true> {
+    cx<R> v[L];
+    __device__ __forceinline__ ChunkCoef(const LineCoef<R> &C, int start) {
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            const int i = start + t;
+            const cx<R> x = C.cp[min(i, C.head - 1)];
+            v[t] = i < C.head ? x : C.cp_inf;
+        }
+    }
+    __device__ __forceinline__ cx<R> operator[](int t) const { return v[t]; }
+};
+
+// Forward sweep of one chunk with zero carry-in; r holds (I - sT)u / o on
+// entry and the partial y on exit.  Returns the last y (0 if empty).
+template <typename R, int L, typename CC>
+__device__ __forceinline__ cx<R> fwd_local(cx<R> (&r)[L], int len, const CC &cpl) {
     cx<R> prev = czero<R>();
 #pragma unroll
     for (int t = 0; t < L; ++t) {
         if (t < len) {
-            const int i = start + t;
-            prev = inv[i] * r[t] - cp[i] * prev;
+            prev = cpl[t] * (r[t] - prev);
             r[t] = prev;
         }
     }
@@ -143,52 +190,52 @@ __device__ __forceinline__ cx<R> fwd_local(cx<R> (&r)[L], int start, int len,
 }
 
 // Adds the carried-in term: e_i = -c'_i e_{i-1}, e_{start-1} = carry.
-template <typename R, int L>
-__device__ __forceinline__ void fwd_fix(cx<R> (&r)[L], int start, int len,
-                                        const cx<R> *__restrict__ cp, cx<R> carry) {
+template <typename R, int L, typename CC>
+__device__ __forceinline__ void fwd_fix(cx<R> (&r)[L], int len, const CC &cpl, cx<R> carry) {
     cx<R> e = carry;
 #pragma unroll
     for (int t = 0; t < L; ++t) {
         if (t < len) {
-            e = czero<R>() - cp[start + t] * e;
+            e = czero<R>() - cpl[t] * e;
             r[t] = r[t] + e;
         }
     }
 }
 
-// Back substitution of one chunk with zero carry-in from the right.
-// Returns the first x (0 if empty).
-template <typename R, int L>
-__device__ __forceinline__ cx<R> bwd_local(cx<R> (&r)[L], int start, int len,
-                                           const cx<R> *__restrict__ cp) {
+// Back substitution x_i = y_i - c'_i x_{i+1} of one chunk with zero carry-in
+// from the right.  Returns the first x (0 if empty).
+template <typename R, int L, typename CC>
+__device__ __forceinline__ cx<R> bwd_local(cx<R> (&r)[L], int len, const CC &cpl) {
 #pragma unroll
     for (int t = L - 2; t >= 0; --t) {
-        if (t + 1 < len) r[t] = r[t] - cp[start + t] * r[t + 1];
+        if (t + 1 < len) r[t] = r[t] - cpl[t] * r[t + 1];
     }
     return len > 0 ? r[0] : czero<R>();
 }
 
-template <typename R, int L>
-__device__ __forceinline__ void bwd_fix(cx<R> (&r)[L], int start, int len,
-                                        const cx<R> *__restrict__ cp, cx<R> carry) {
+template <typename R, int L, typename CC>
+__device__ __forceinline__ void bwd_fix(cx<R> (&r)[L], int len, const CC &cpl, cx<R> carry) {
     cx<R> e = carry;
 #pragma unroll
     for (int t = L - 1; t >= 0; --t) {
         if (t < len) {
-            e = czero<R>() - cp[start + t] * e;
+            e = czero<R>() - cpl[t] * e;
             r[t] = r[t] + e;
         }
     }
 }
 
 // Inclusive scan over the lanes lane, lane-STRIDE, lane-2*STRIDE, ... of the
-// wavefront of the affine maps (A, B): afterwards (A, B) maps the value before
-// the first chunk of this wavefront to the value after this lane's chunk.
+// wavefront of the affine maps (A, B), over 2^levels - 1 predecessors:
+// afterwards (A, B) maps the value before the window to the value after
+// this lane's chunk (all earlier chunks contribute below rounding).
 template <typename R, int STRIDE>
-__device__ __forceinline__ void wave_scan_up(cx<R> &A, cx<R> &B) {
+__device__ __forceinline__ void wave_scan_up(cx<R> &A, cx<R> &B, int levels) {
     const int lane = threadIdx.x & 63;
+    int lv = 0;
 #pragma unroll
-    for (int d = STRIDE; d < 64; d <<= 1) {
+    for (int d = STRIDE; d < 64; d <<= 1, ++lv) {
+        if (lv >= levels) break;
         const cx<R> Ap = shfl_up(A, d), Bp = shfl_up(B, d);
         if (lane >= d) {
             B = cfma(A, Bp, B);
@@ -198,10 +245,12 @@ __device__ __forceinline__ void wave_scan_up(cx<R> &A, cx<R> &B) {
 }
 
 template <typename R, int STRIDE>
-__device__ __forceinline__ void wave_scan_down(cx<R> &A, cx<R> &B) {
+__device__ __forceinline__ void wave_scan_down(cx<R> &A, cx<R> &B, int levels) {
     const int lane = threadIdx.x & 63;
+    int lv = 0;
 #pragma unroll
-    for (int d = STRIDE; d < 64; d <<= 1) {
+    for (int d = STRIDE; d < 64; d <<= 1, ++lv) {
+        if (lv >= levels) break;
         const cx<R> Ap = shfl_down(A, d), Bp = shfl_down(B, d);
         if (lane + d < 64) {
             B = cfma(A, Bp, B);
@@ -211,30 +260,98 @@ __device__ __forceinline__ void wave_scan_down(cx<R> &A, cx<R> &B) {
 }
 
 // Solves one line held by the 64 lanes of a wavefront (lane k owns
-// [start, start+len)).  Ak = product of -c'_i over the lane's chunk.
-template <typename R, int L>
-__device__ __forceinline__ void solve_line_wave(cx<R> (&r)[L], int start, int len,
-                                                const cx<R> *__restrict__ inv,
-                                                const cx<R> *__restrict__ cp, cx<R> Ak) {
+// [start, start+len)).
+template <typename R, int L, bool GENERAL>
+__device__ __forceinline__ void solve_line_wave(cx<R> (&r)[L], int start, int len, const LineCoef<R> &C) {
     const int lane = threadIdx.x & 63;
+    const ChunkCoef<R, L, GENERAL> cpl(C, start);
+    const cx<R> Ak = C.chunkA[lane];
     cx<R> A = Ak;
-    cx<R> B = fwd_local<R, L>(r, start, len, inv, cp);
-    wave_scan_up<R, 1>(A, B);
+    cx<R> B = fwd_local<R, L>(r, len, cpl);
+    wave_scan_up<R, 1>(A, B, C.levels);
     cx<R> carry = shfl_up(B, 1);
     if (lane == 0) carry = czero<R>();
-    fwd_fix<R, L>(r, start, len, cp, carry);
+    fwd_fix<R, L>(r, len, cpl, carry);
     A = Ak;
-    B = bwd_local<R, L>(r, start, len, cp);
-    wave_scan_down<R, 1>(A, B);
+    B = bwd_local<R, L>(r, len, cpl);
+    wave_scan_down<R, 1>(A, B, C.levels);
     carry = shfl_down(B, 1);
     if (lane == 63) carry = czero<R>();
-    bwd_fix<R, L>(r, start, len, cp, carry);
+    bwd_fix<R, L>(r, len, cpl, carry);
 }
 
 // LDS index of point i with one padding slot after every chunk of L points,
 // so that the 64 lanes reading "their" chunk hit distinct banks.
 template <int L> __device__ __forceinline__ int sidx(int i) { return i + i / L; }
 template <int L> __host__ __device__ constexpr int srow(int n) { return n + n / L + 1; }
+
+// Right-hand side (I - sT) u of the x-line solve for component J over the
+// lane's chunk, where u = psi + SO update:
+//   u_J(i) = s_J(i) + ys_J(i) + sum_j' q[J][j'] (s_j'(i+1) - s_j'(i-1)),
+// with s the staged row (zero outside [0, nx)) and ys optional precomputed
+// y-derivative terms.  A sliding window reads every staged value once.
+template <typename R, int L, int J>
+__device__ __forceinline__ void build_rhs(const cx<R> *s, const cx<R> *ys, int ld, int nx, int start, int len,
+                                          const cx<R> *q, unsigned qmask, cx<R> rdiag, cx<R> roff,
+                                          cx<R> (&r)[L]) {
+    auto at = [&](int jp, int i) -> cx<R> {
+        return (i >= 0 && i < nx) ? s[jp * ld + sidx<L>(i)] : czero<R>();
+    };
+    const bool use0 = qmask & (1u << (3 * J + 0)), use1 = qmask & (1u << (3 * J + 1)),
+               use2 = qmask & (1u << (3 * J + 2));
+    const cx<R> q0 = q[3 * J + 0], q1 = q[3 * J + 1], q2 = q[3 * J + 2];
+    // window of the coupled components at i-1 and i+1, own component at i
+    cx<R> m0{}, m1{}, m2{}, p0{}, p1{}, p2{}, c0{}, c1{}, c2{};
+    auto load_win = [&](int i) {
+        if (use0) { m0 = at(0, i - 1); c0 = at(0, i); p0 = at(0, i + 1); }
+        if (use1) { m1 = at(1, i - 1); c1 = at(1, i); p1 = at(1, i + 1); }
+        if (use2) { m2 = at(2, i - 1); c2 = at(2, i); p2 = at(2, i + 1); }
+    };
+    auto shift_win = [&](int i) {  // window moves from i-1 to i
+        if (use0) { m0 = c0; c0 = p0; p0 = at(0, i + 1); }
+        if (use1) { m1 = c1; c1 = p1; p1 = at(1, i + 1); }
+        if (use2) { m2 = c2; c2 = p2; p2 = at(2, i + 1); }
+    };
+    auto u_at = [&](int i) -> cx<R> {
+        if (i < 0 || i >= nx) return czero<R>();
+        cx<R> v = at(J, i);
+        if (ys) v = v + ys[J * ld + sidx<L>(i)];
+        if (use0) v = cfma(q0, p0 - m0, v);
+        if (use1) v = cfma(q1, p1 - m1, v);
+        if (use2) v = cfma(q2, p2 - m2, v);
+        return v;
+    };
+    if (len <= 0) {
+#pragma unroll
+        for (int t = 0; t < L; ++t) r[t] = czero<R>();
+        return;
+    }
+    load_win(start - 1);
+    cx<R> um = u_at(start - 1);
+    shift_win(start);
+    cx<R> uc = u_at(start);
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        if (t < len) {
+            shift_win(start + t + 1);
+            const cx<R> un = u_at(start + t + 1);
+            r[t] = cfma(roff, um + un, rdiag * uc);
+            um = uc;
+            uc = un;
+        } else {
+            r[t] = czero<R>();
+        }
+    }
+}
+
+template <typename R, int L>
+__device__ __forceinline__ void build_rhs_any(int J, const cx<R> *s, const cx<R> *ys, int ld, int nx, int start,
+                                              int len, const cx<R> *q, unsigned qmask, cx<R> rdiag, cx<R> roff,
+                                              cx<R> (&r)[L]) {
+    if (J == 0) build_rhs<R, L, 0>(s, ys, ld, nx, start, len, q, qmask, rdiag, roff, r);
+    else if (J == 1) build_rhs<R, L, 1>(s, ys, ld, nx, start, len, q, qmask, rdiag, roff, r);
+    else build_rhs<R, L, 2>(s, ys, ld, nx, start, len, q, qmask, rdiag, roff, r);
+}
 
 // ------------------------------------------------------------- x-pass ---
 template <typename R> struct XArgs {
@@ -246,7 +363,7 @@ template <typename R> struct XArgs {
     Model<R> m;
     const double *dscale;      // RENORM factors to apply first, or nullptr
     int pointwise;             // 1: CALCNU + HERM in this pass
-    const cx<R> *inv, *cp, *chunkA;  // CN_x tables (nx, nx, 64 entries)
+    LineCoef<R> cx_;           // CN_x elimination coefficients (64 chunks)
     cx<R> rdiag, roff;         // right-hand side (I - sT): diagonal, off-diagonal
     cx<R> qx[9];               // SO: psi'_j += sum_j' qx[j][j'] (psi_j'(i+1) - psi_j'(i-1))
     unsigned qxmask;           // bit 3j+j' set where qx[j][j'] != 0
@@ -255,44 +372,132 @@ template <typename R> struct XArgs {
     unsigned qymask;
 };
 
-constexpr int XPASS_THREADS = 192;
+constexpr int XPASS_THREADS = 256;
+constexpr int ROW_THREADS = 192;  // 1D and adjoint row kernels: 3 wavefronts
 
-template <typename R, int L>
+// Whole-wavefront rotations by one lane (DPP wave_ror:1 / wave_rol:1):
+// ror1 gives lane l the value of lane l-1 (lane 0 gets lane 63), rol1 the
+// value of lane l+1 (lane 63 gets lane 0).  Every lane must execute them.
+__device__ __forceinline__ unsigned dpp_ror1(unsigned v) { return __builtin_amdgcn_update_dpp(0u, v, 0x13C, 0xF, 0xF, false); }
+__device__ __forceinline__ unsigned dpp_rol1(unsigned v) { return __builtin_amdgcn_update_dpp(0u, v, 0x134, 0xF, 0xF, false); }
+__device__ __forceinline__ double ror1(double x) {
+    const unsigned long long u = __double_as_longlong(x);
+    const unsigned lo = dpp_ror1((unsigned)u), hi = dpp_ror1((unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double rol1(double x) {
+    const unsigned long long u = __double_as_longlong(x);
+    const unsigned lo = dpp_rol1((unsigned)u), hi = dpp_rol1((unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float ror1(float x) { return __uint_as_float(dpp_ror1(__float_as_uint(x))); }
+__device__ __forceinline__ float rol1(float x) { return __uint_as_float(dpp_rol1(__float_as_uint(x))); }
+template <typename R> __device__ __forceinline__ cx<R> ror1(cx<R> v) { return {ror1(v.x), ror1(v.y)}; }
+template <typename R> __device__ __forceinline__ cx<R> rol1(cx<R> v) { return {rol1(v.x), rol1(v.y)}; }
+
+// x-pass: one workgroup of 4 wavefronts per row.  Wavefront w owns the
+// contiguous points w*RW + 64k + lane (k < K, RW = 64K, K = ceil(nx/256)),
+// so neighbours i-1, i+1 are the adjacent lanes (DPP rotations), the
+// previous / next k at the wrap-around lanes, and a two-value exchange
+// through LDS between wavefronts.  In this layout the pass applies the
+// previous RENORM, CALCNU and HERM, the SO update and the Crank-Nicolson
+// right-hand side.  The three lines are then transposed one component at a
+// time through one LDS row (so a workgroup needs only one row of LDS) into
+// the chunk layout, solved by wavefronts 0-2, and transposed back for
+// coalesced stores.
+template <typename R, int L, bool GENERAL>
 __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
+    constexpr int KM = (64 * L + XPASS_THREADS - 1) / XPASS_THREADS;  // max points per lane
     extern __shared__ unsigned char smem_raw[];
-    cx<R> *s = reinterpret_cast<cx<R> *>(smem_raw);
+    cx<R> *B = reinterpret_cast<cx<R> *>(smem_raw);  // one staged line
     const int nx = a.nx;
-    const int ld = srow<L>(nx);
-    cx<R> *ys = s + 3 * ld;  // y-derivative SO terms (so_y only)
+    cx<R> *E = B + srow<L>(nx);  // edge exchange: [2][4 waves][2 ends][3 comps]
     const int row = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int K = (nx + XPASS_THREADS - 1) / XPASS_THREADS;
+    const int RW = 64 * K;
     const long long roff = (long long)row * nx;
     const cx<R> *src = a.src + roff;
 
-    R d0 = R(1), d1 = R(1), d2 = R(1);
-    if (a.dscale) {
-        d0 = R(a.dscale[0]);
-        d1 = R(a.dscale[1]);
-        d2 = R(a.dscale[2]);
+    // ---- load, RENORM scale, CALCNU + HERM
+    cx<R> v[3][KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const int i = w * RW + 64 * k + lane;
+        const bool ok = k < K && i < nx;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v[j][k] = ok ? src[j * a.plane + i] : czero<R>();
     }
-    const R yv = a.y0 + R(row) * a.dy;
-    const R vy = R(0.5) * a.m.kappa2 * yv * yv;
-    for (int i = tid; i < nx; i += XPASS_THREADS) {
-        cx<R> p = src[i], z = src[a.plane + i], m = src[2 * a.plane + i];
+    {
+        R d0 = R(1), d1 = R(1), d2 = R(1);
         if (a.dscale) {
-            p = d0 * p;
-            z = d1 * z;
-            m = d2 * m;
+            d0 = R(a.dscale[0]);
+            d1 = R(a.dscale[1]);
+            d2 = R(a.dscale[2]);
         }
-        if (a.pointwise) {
-            const R xv = a.x0 + R(i) * a.dx;
-            pointwise(p, z, m, R(0.5) * xv * xv + vy, a.m);
+        const R yv = a.y0 + R(row) * a.dy;
+        const R vy = R(0.5) * a.m.kappa2 * yv * yv;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = w * RW + 64 * k + lane;
+            if (k < K && i < nx) {
+                if (a.dscale) {
+                    v[0][k] = d0 * v[0][k];
+                    v[1][k] = d1 * v[1][k];
+                    v[2][k] = d2 * v[2][k];
+                }
+                if (a.pointwise) {
+                    const R xv = a.x0 + R(i) * a.dx;
+                    pointwise(v[0][k], v[1][k], v[2][k], R(0.5) * xv * xv + vy, a.m);
+                }
+            }
         }
-        const int si = sidx<L>(i);
-        s[si] = p;
-        s[ld + si] = z;
-        s[2 * ld + si] = m;
-        if (a.so_y) {
+    }
+
+    // neighbour values at i-1 / i+1 of x[k] for all three components
+    auto exchange_edges = [&](cx<R> (&x)[3][KM], int round) {
+        cx<R> *Er = E + round * 24;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if (lane == 0 && k == 0) Er[(w * 2 + 0) * 3 + j] = x[j][k];
+                if (lane == 63 && k == K - 1) Er[(w * 2 + 1) * 3 + j] = x[j][k];
+            }
+        }
+    };
+    auto neighbours = [&](cx<R> (&x)[3][KM], int round, int j, int k, cx<R> &prev, cx<R> &next) {
+        const cx<R> *Er = E + round * 24;
+        const cx<R> r0 = ror1(x[j][k]);
+        const cx<R> rm = ror1(x[j][k > 0 ? k - 1 : 0]);
+        const cx<R> l0 = rol1(x[j][k]);
+        const cx<R> lp = rol1(x[j][k + 1 < KM ? k + 1 : k]);
+        prev = r0;
+        next = l0;
+        if (lane == 0) prev = k > 0 ? rm : (w > 0 ? Er[((w - 1) * 2 + 1) * 3 + j] : czero<R>());
+        if (lane == 63) next = k < K - 1 ? lp : (w < 3 ? Er[((w + 1) * 2 + 0) * 3 + j] : czero<R>());
+    };
+
+    // ---- SO update u = v + q (v(i+1) - v(i-1)) [+ y-derivative terms]
+    exchange_edges(v, 0);
+    __syncthreads();
+    cx<R> u[3][KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        cx<R> pv[3], nv[3];
+#pragma unroll
+        for (int jp = 0; jp < 3; ++jp) neighbours(v, 0, jp, k, pv[jp], nv[jp]);
+        const int i = w * RW + 64 * k + lane;
+        const bool ok = k < K && i < nx;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<R> t = v[j][k];
+#pragma unroll
+            for (int jp = 0; jp < 3; ++jp)
+                if (a.qxmask & (1u << (3 * j + jp))) t = cfma(a.qx[3 * j + jp], nv[jp] - pv[jp], t);
+            u[j][k] = ok ? t : czero<R>();
+        }
+        if (a.so_y && ok) {
             cx<R> up[3], dn[3];
 #pragma unroll
             for (int jp = 0; jp < 3; ++jp) {
@@ -300,68 +505,63 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
                 dn[jp] = row >= 1 ? src[jp * a.plane - nx + i] : czero<R>();
             }
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                cx<R> acc = czero<R>();
+            for (int j = 0; j < 3; ++j)
 #pragma unroll
                 for (int jp = 0; jp < 3; ++jp)
-                    if (a.qymask & (1u << (3 * j + jp))) acc = cfma(a.qy[3 * j + jp], up[jp] - dn[jp], acc);
-                ys[j * ld + si] = acc;
-            }
+                    if (a.qymask & (1u << (3 * j + jp))) u[j][k] = cfma(a.qy[3 * j + jp], up[jp] - dn[jp], u[j][k]);
         }
     }
-    __syncthreads();
 
-    const int j = tid >> 6, lane = tid & 63;
+    // ---- right-hand side (I - sT) u / o
+    exchange_edges(u, 1);
+    __syncthreads();
+    cx<R> r[3][KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const int i = w * RW + 64 * k + lane;
+        const bool ok = k < K && i < nx;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<R> pu, nu;
+            neighbours(u, 1, j, k, pu, nu);
+            r[j][k] = ok ? cfma(a.roff, pu + nu, a.rdiag * u[j][k]) : czero<R>();
+        }
+    }
+
+    // ---- transpose each component into the chunk layout, solve, transpose back
     const int start = lane * L;
     const int len = max(0, min(L, nx - start));
-    const cx<R> *sj = s + j * ld;
-    // value after the SO sub-step at point i of component j (zero outside)
-    auto so_at = [&](int i) -> cx<R> {
-        if (i < 0 || i >= nx) return czero<R>();
-        cx<R> v = sj[sidx<L>(i)];
-        if (a.so_y) v = v + ys[j * ld + sidx<L>(i)];
+    cx<R> c[L];
 #pragma unroll
-        for (int jp = 0; jp < 3; ++jp) {
-            if (a.qxmask & (1u << (3 * j + jp))) {
-                const cx<R> fp = i + 1 < nx ? s[jp * ld + sidx<L>(i + 1)] : czero<R>();
-                const cx<R> fm = i >= 1 ? s[jp * ld + sidx<L>(i - 1)] : czero<R>();
-                v = cfma(a.qx[3 * j + jp], fp - fm, v);
-            }
+    for (int jj = 0; jj < 3; ++jj) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = w * RW + 64 * k + lane;
+            if (k < K && i < nx) B[sidx<L>(i)] = r[jj][k];
         }
-        return v;
-    };
-    cx<R> r[L];
-    cx<R> um = czero<R>(), uc = czero<R>();
-    if (len > 0) {
-        um = so_at(start - 1);
-        uc = so_at(start);
-    }
+        __syncthreads();
+        if (w == jj) {
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-        if (t < len) {
-            const cx<R> un = so_at(start + t + 1);
-            r[t] = cfma(a.roff, um + un, a.rdiag * uc);
-            um = uc;
-            uc = un;
-        } else {
-            r[t] = czero<R>();
+            for (int t = 0; t < L; ++t) c[t] = t < len ? B[sidx<L>(start + t)] : czero<R>();
         }
     }
-    __syncthreads();  // every read of the staged row is done
-
-    solve_line_wave<R, L>(r, start, len, a.inv, a.cp, a.chunkA[lane]);
-    cx<R> *wj = s + j * ld;
-#pragma unroll
-    for (int t = 0; t < L; ++t)
-        if (t < len) wj[sidx<L>(start + t)] = r[t];
-    __syncthreads();
-
+    if (w < 3) solve_line_wave<R, L, GENERAL>(c, start, len, a.cx_);
     cx<R> *dst = a.dst + roff;
-    for (int i = tid; i < nx; i += XPASS_THREADS) {
-        const int si = sidx<L>(i);
-        dst[i] = s[si];
-        dst[a.plane + i] = s[ld + si];
-        dst[2 * a.plane + i] = s[2 * ld + si];
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+        __syncthreads();
+        if (w == jj) {
+#pragma unroll
+            for (int t = 0; t < L; ++t)
+                if (t < len) B[sidx<L>(start + t)] = c[t];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = w * RW + 64 * k + lane;
+            if (k < K && i < nx) dst[jj * a.plane + i] = B[sidx<L>(i)];
+        }
     }
 }
 
@@ -370,7 +570,7 @@ template <typename R> struct YArgs {
     cx<R> *psi;                // state, updated in place
     int nx, ny;
     long long plane;
-    const cx<R> *inv, *cp, *chunkA;  // CN_y tables (ny, ny, blockDim/TX entries)
+    LineCoef<R> cy;            // CN_y elimination coefficients (blockDim/TX chunks)
     cx<R> rdiag, roff;
     double *norm_partials;     // [3][gridDim.x] sums of |psi|^2, or nullptr
 };
@@ -379,16 +579,24 @@ constexpr int YPASS_MAX_THREADS = 512;
 constexpr int YPASS_MAX_WAVES = YPASS_MAX_THREADS / 64;
 
 // Workgroup: TX adjacent columns x P chunks of L rows (blockDim = TX * P);
-// lane tid holds column tid % TX, chunk tid / TX.  grid = (ceil(nx/TX), 3).
-template <typename R, int L, int TX>
+// lane tid holds column tid % TX, chunk tid / TX.  grid = (ceil(nx/TX), 3):
+// one workgroup per (tile, component).
+template <typename R, int L, int TX, bool GENERAL>
 __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
     __shared__ cx<R> scA[2][YPASS_MAX_WAVES][TX], scB[2][YPASS_MAX_WAVES][TX];
     __shared__ double red[YPASS_MAX_WAVES];
     const int nx = a.nx, ny = a.ny;
-    const int j = blockIdx.y;
+    // Workgroups are dispatched round-robin over the 8 XCDs; map them so that
+    // each XCD takes a contiguous range of tiles, keeping the two tiles that
+    // share a 128-byte line in one L2.
+    const int ntx = gridDim.x;
+    const int nb = ntx * gridDim.y;
+    const int b = blockIdx.x + ntx * blockIdx.y;
+    const int tile = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int j = tile / ntx, tx = tile % ntx;
     const int tid = threadIdx.x, c = tid % TX, k = tid / TX;
     const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    const int x = blockIdx.x * TX + c;
+    const int x = tx * TX + c;
     const bool valid = x < nx;
     const int start = k * L;
     const int len = valid ? max(0, min(L, ny - start)) : 0;
@@ -411,11 +619,12 @@ __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
         }
     }
 
-    const cx<R> Ak = a.chunkA[k];
+    const ChunkCoef<R, L, GENERAL> cpl(a.cy, start);
+    const cx<R> Ak = a.cy.chunkA[k];
     // forward sweep and its scan over the chunks of each column
     cx<R> A = Ak;
-    cx<R> B = fwd_local<R, L>(r, start, len, a.inv, a.cp);
-    wave_scan_up<R, TX>(A, B);
+    cx<R> B = fwd_local<R, L>(r, len, cpl);
+    wave_scan_up<R, TX>(A, B, a.cy.levels);
     if (lane >= 64 - TX) {
         scA[0][wave][c] = A;
         scB[0][wave][c] = B;
@@ -428,12 +637,12 @@ __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
         const cx<R> prev = shfl_up(incl, TX);
         if (lane >= TX) carry = prev;
     }
-    fwd_fix<R, L>(r, start, len, a.cp, carry);
+    fwd_fix<R, L>(r, len, cpl, carry);
 
     // back substitution and its reverse scan
     A = Ak;
-    B = bwd_local<R, L>(r, start, len, a.cp);
-    wave_scan_down<R, TX>(A, B);
+    B = bwd_local<R, L>(r, len, cpl);
+    wave_scan_down<R, TX>(A, B, a.cy.levels);
     if (lane < TX) {
         scA[1][wave][c] = A;
         scB[1][wave][c] = B;
@@ -446,7 +655,7 @@ __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
         const cx<R> next = shfl_down(incl, TX);
         if (lane < 64 - TX) carry = next;
     }
-    bwd_fix<R, L>(r, start, len, a.cp, carry);
+    bwd_fix<R, L>(r, len, cpl, carry);
 
     double nrm = 0.0;
 #pragma unroll
@@ -464,7 +673,7 @@ __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
         if (tid == 0) {
             double t = 0.0;
             for (int w = 0; w < nw; ++w) t += red[w];
-            a.norm_partials[(long long)j * gridDim.x + blockIdx.x] = t;
+            a.norm_partials[(long long)j * ntx + tx] = t;
         }
     }
 }
@@ -532,35 +741,6 @@ __device__ __forceinline__ void renorm_factors(const RenormSpec &sp, const doubl
     d[0] = d[1] = d[2] = dd;
 }
 
-// Sums the per-tile |psi|^2 partials (fixed order) and writes
-// out = {d_+1, d_0, d_-1, N_+1, N_0, N_-1, fallback}.
-__global__ void __launch_bounds__(256) renorm_finalize_kernel(const double *partials, int ntiles,
-                                                              RenormSpec sp, double *out) {
-    __shared__ double red[3][256];
-    const int t = threadIdx.x;
-    for (int j = 0; j < 3; ++j) {
-        double s = 0.0;
-        for (int q = t; q < ntiles; q += 256) s += partials[(long long)j * ntiles + q];
-        red[j][t] = s;
-    }
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (t < w)
-            for (int j = 0; j < 3; ++j) red[j][t] += red[j][t + w];
-        __syncthreads();
-    }
-    if (t == 0) {
-        double N[3] = {red[0][0] * sp.dA, red[1][0] * sp.dA, red[2][0] * sp.dA};
-        double d[3], fb = 0.0;
-        renorm_factors(sp, N, d, &fb);
-        for (int j = 0; j < 3; ++j) {
-            out[j] = d[j];
-            out[3 + j] = N[j];
-        }
-        out[6] = fb;
-    }
-}
-
 template <typename R>
 __global__ void __launch_bounds__(256) scale_kernel(cx<R> *psi, long long plane, const double *d) {
     const R d0 = R(d[0]), d1 = R(d[1]), d2 = R(d[2]);
@@ -581,7 +761,7 @@ template <typename R> struct Args1D {
     int nx, nsteps;
     R dx, x0;
     Model<R> m;
-    const cx<R> *inv, *cp, *chunkA;
+    LineCoef<R> cx_;
     cx<R> rdiag, roff;
     cx<R> qx[9];
     unsigned qxmask;
@@ -589,8 +769,8 @@ template <typename R> struct Args1D {
     double *renorm_out;        // last step's {d, N, fallback}, or nullptr
 };
 
-template <typename R, int L>
-__global__ void __launch_bounds__(XPASS_THREADS) step1d_kernel(Args1D<R> a) {
+template <typename R, int L, bool GENERAL>
+__global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
     extern __shared__ unsigned char smem_raw[];
     cx<R> *s = reinterpret_cast<cx<R> *>(smem_raw);
     __shared__ double red[3];
@@ -602,16 +782,15 @@ __global__ void __launch_bounds__(XPASS_THREADS) step1d_kernel(Args1D<R> a) {
     const int start = lane * L;
     const int len = max(0, min(L, nx - start));
 
-    for (int i = tid; i < nx; i += XPASS_THREADS) {
+    for (int i = tid; i < nx; i += ROW_THREADS) {
         const int si = sidx<L>(i);
         s[si] = a.psi[i];
         s[ld + si] = a.psi[nx + i];
         s[2 * ld + si] = a.psi[2 * nx + i];
     }
     __syncthreads();
-    const cx<R> *sj = s + j * ld;
     for (int step = 0; step < a.nsteps; ++step) {
-        for (int i = tid; i < nx; i += XPASS_THREADS) {
+        for (int i = tid; i < nx; i += ROW_THREADS) {
             const int si = sidx<L>(i);
             cx<R> p = s[si], z = s[ld + si], m = s[2 * ld + si];
             const R xv = a.x0 + R(i) * a.dx;
@@ -621,38 +800,10 @@ __global__ void __launch_bounds__(XPASS_THREADS) step1d_kernel(Args1D<R> a) {
             s[2 * ld + si] = m;
         }
         __syncthreads();
-        auto so_at = [&](int i) -> cx<R> {
-            if (i < 0 || i >= nx) return czero<R>();
-            cx<R> v = sj[sidx<L>(i)];
-#pragma unroll
-            for (int jp = 0; jp < 3; ++jp) {
-                if (a.qxmask & (1u << (3 * j + jp))) {
-                    const cx<R> fp = i + 1 < nx ? s[jp * ld + sidx<L>(i + 1)] : czero<R>();
-                    const cx<R> fm = i >= 1 ? s[jp * ld + sidx<L>(i - 1)] : czero<R>();
-                    v = cfma(a.qx[3 * j + jp], fp - fm, v);
-                }
-            }
-            return v;
-        };
         cx<R> r[L];
-        cx<R> um = czero<R>(), uc = czero<R>();
-        if (len > 0) {
-            um = so_at(start - 1);
-            uc = so_at(start);
-        }
-#pragma unroll
-        for (int t = 0; t < L; ++t) {
-            if (t < len) {
-                const cx<R> un = so_at(start + t + 1);
-                r[t] = cfma(a.roff, um + un, a.rdiag * uc);
-                um = uc;
-                uc = un;
-            } else {
-                r[t] = czero<R>();
-            }
-        }
+        build_rhs_any<R, L>(j, s, nullptr, ld, nx, start, len, a.qx, a.qxmask, a.rdiag, a.roff, r);
         __syncthreads();
-        solve_line_wave<R, L>(r, start, len, a.inv, a.cp, a.chunkA[lane]);
+        solve_line_wave<R, L, GENERAL>(r, start, len, a.cx_);
         if (a.m.imag) {
             double nrm = 0.0;
 #pragma unroll
@@ -684,7 +835,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) step1d_kernel(Args1D<R> a) {
             if (t < len) wj[sidx<L>(start + t)] = r[t];
         __syncthreads();
     }
-    for (int i = tid; i < nx; i += XPASS_THREADS) {
+    for (int i = tid; i < nx; i += ROW_THREADS) {
         const int si = sidx<L>(i);
         a.psi[i] = s[si];
         a.psi[nx + i] = s[ld + si];

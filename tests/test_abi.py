@@ -41,7 +41,7 @@ def test_version(lib):
 @pytest.mark.parametrize("args,fragment", [
     ((3, 16, 16, 0.1, 0.1, 0), b"dim"),
     ((2, 0, 16, 0.1, 0.1, 0), b"nx"),
-    ((2, 4097, 16, 0.1, 0.1, 1), b"nx"),
+    ((2, 2049, 16, 0.1, 0.1, 1), b"nx"),
     ((2, 2049, 16, 0.1, 0.1, 0), b"nx"),
     ((2, 16, 2049, 0.1, 0.1, 0), b"ny"),
     ((2, 16, 16, -0.1, 0.1, 0), b"spacing"),
