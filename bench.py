@@ -73,6 +73,46 @@ def cpu_baseline(w, psi0, seconds: float):
                       f"({el:.1f} s, FP64, OpenMP over grid lines)"}
 
 
+def adjoint_ratio(reps: int = 2):
+    """Forward and backward (recompute + adjoint) times of the differentiable
+    512^2 real-time workload: 2000 steps, 100 Omega segments, checkpoints
+    every ceil(sqrt(2000)) = 45 steps, loss = dA sum |psi_{+1}(T)|^2."""
+    import time as _t
+
+    import torch
+
+    from paper_2009_13507_amd import autograd
+    from paper_2009_13507_amd import workloads as W
+
+    w = W.W2D_ADJ
+    psi0 = W.interpolate(W.ground_256(), W.W2D_IMAG.nx, W.W2D_IMAG.dx, w.nx, w.dx)
+    omega = W.omega_schedule(100, seed=2)
+    prob = autograd.RealTimeProblem(dx=w.dx, dy=w.dy, dt=w.dt, steps=w.steps, steps_per_seg=w.steps // 100,
+                                    c0=w.c0, c2=w.c2, gamma=w.gamma, so=w.so)
+    dev = torch.device("cuda:0")
+    best = None
+    for _ in range(reps):
+        p0 = torch.from_numpy(psi0).to(dev).requires_grad_(True)
+        om = torch.tensor(omega, dtype=torch.float64, device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        out = autograd.propagate(p0, om, prob)
+        torch.cuda.synchronize()
+        t1 = _t.perf_counter()
+        loss = w.dx * w.dy * (out[0].abs() ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = _t.perf_counter()
+        cur = (t1 - t0, t2 - t1)
+        if best is None or sum(cur) < sum(best):
+            best = cur
+    tf, tb = best
+    return {"workload": w.name, "steps": w.steps, "omega_segments": 100, "checkpoint_every": prob.interval(),
+            "t_forward_s": tf, "t_backward_s": tb, "R_b": tb / tf, "R_t": (tf + tb) / tf,
+            "grad_norm_psi0": float(p0.grad.abs().pow(2).sum().sqrt()),
+            "grad_omega_first": float(om.grad[0])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +123,7 @@ def main():
     ap.add_argument("--profile-every", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint cost ratio")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run torch copies of the state size (counter calibration)")
     args = ap.parse_args()
@@ -169,6 +210,8 @@ def main():
                      "algorithmic_bytes_per_launch": per_launch},
         "final_observables": {k: obs_log[-1][k] for k in ("N", "M", "E", "rms")},
     }
+    if not args.no_adjoint and args.dtype == "f64":
+        line["adjoint_cost_ratio"] = adjoint_ratio()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, psi0, args.cpu_seconds)
     print(json.dumps(line), flush=True)

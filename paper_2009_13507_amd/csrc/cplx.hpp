@@ -52,12 +52,12 @@ __host__ __device__ constexpr double inv_fact(int n) {
     return 1.0 / f;
 }
 
-template <typename R, bool ALT, int ODD>
+template <typename R, bool ALT, int ODD, int NT = 10>
 __host__ __device__ __forceinline__ R series_q(R q) {
-    // sum_{k=0}^{9} s^k q^k / (2k+ODD)!, s = -1 if ALT
-    R acc = R(inv_fact(18 + ODD));
+    // sum_{k=0}^{NT-1} s^k q^k / (2k+ODD)!, s = -1 if ALT
+    R acc = R(inv_fact(2 * (NT - 1) + ODD));
 #pragma unroll
-    for (int k = 8; k >= 0; --k) {
+    for (int k = NT - 2; k >= 0; --k) {
         const R c = R(inv_fact(2 * k + ODD));
         acc = ALT ? fma_(-q, acc, c) : fma_(q, acc, c);
     }
@@ -70,5 +70,9 @@ template <typename R> __host__ __device__ __forceinline__ R cosh_q(R q) { return
 
 // Largest u^2 for which the series above are used.
 template <typename R> struct SeriesLimit { static constexpr R q = R(0.6168502750680849); };  // (pi/4)^2
+// Shorter series: with q <= 1e-2 the first omitted term of a 6-term series
+// is below 2e-22 relative, with q <= 1e-4 that of a 4-term series is below
+// 3e-22.  A wavefront takes the shortest series valid for all its lanes.
+constexpr double SERIES_Q6 = 1e-2, SERIES_Q4 = 1e-4;
 
 } // namespace ssgp

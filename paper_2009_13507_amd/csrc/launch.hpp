@@ -16,9 +16,9 @@ struct Launch {
 };
 
 // Dynamic LDS of the x-pass: one staged line (one padding slot per chunk)
-// and the edge exchange area.
+// and the edge exchange area of up to 8 wavefronts.
 template <typename R> inline size_t xpass_lds(int nx, int L) {
-    return ((size_t)(nx + nx / L + 1) + 48) * sizeof(cx<R>);
+    return ((size_t)(nx + nx / L + 1) + 96) * sizeof(cx<R>);
 }
 // Dynamic LDS of the 1D and adjoint row kernels: all three components.
 template <typename R> inline size_t row_lds(int nx, int L) { return (size_t)3 * (nx + nx / L + 1) * sizeof(cx<R>); }

@@ -46,10 +46,14 @@ __device__ __forceinline__ float cosh_(float x) { return coshf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
 
-// cos(th), sin(th); Taylor series for |th| <= pi/4, library call beyond.
+// cos(th), sin(th); Taylor series for |th| <= pi/4 (as short as every lane
+// of the wavefront allows), library call beyond.
 template <typename R> __device__ __forceinline__ void cos_sin(R th, R &c, R &s) {
     const R q = th * th;
-    if (q <= SeriesLimit<R>::q) {
+    if (__all(q <= R(SERIES_Q6))) {
+        s = th * series_q<R, true, 1, 6>(q);
+        c = series_q<R, true, 0, 6>(q);
+    } else if (q <= SeriesLimit<R>::q) {
         s = th * sinc_q(q);
         c = cos_q(q);
     } else {
@@ -93,7 +97,10 @@ __device__ __forceinline__ void pointwise(cx<R> &p, cx<R> &z, cx<R> &m, R V, con
     const cx<R> b = cfma(mk(M.c2, R(0)), conj(z) * p, mk(M.om_t, R(0)));
     const R q = R(0.25) * M.dt * M.dt * (abs2(a) + abs2(b));
     R S, C;
-    if (q <= SeriesLimit<R>::q) {
+    if (__all(q <= R(SERIES_Q4))) {
+        S = M.imag ? series_q<R, false, 1, 4>(q) : series_q<R, true, 1, 4>(q);
+        C = M.imag ? series_q<R, false, 0, 4>(q) : series_q<R, true, 0, 4>(q);
+    } else if (q <= SeriesLimit<R>::q) {
         S = M.imag ? sinhc_q(q) : sinc_q(q);
         C = M.imag ? cosh_q(q) : cos_q(q);
     } else {
