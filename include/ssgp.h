@@ -162,22 +162,51 @@ int ssgp_omega_grad(ssgp_grid g, double *out, int nseg, int reset);
 int ssgp_destroy(ssgp_grid g);
 
 /* Batched imaginary-time stepping of n independent 2D grids held in one
- * device pool: grid i is nx[i] x ny[i] with spacing dx[i] (dy = dx), state at
- * pool_dev + offsets[i] elements (3*ny*nx elements each), parameters p[i].
- * The arrays are copied. */
+ * device pool (the same step as ssgp_step_imag, App. A, per grid).  Grid i
+ * is nx[i] x ny[i] points (1 <= nx, ny <= 512) with spacing dx[i] in both
+ * directions, its state at pool_dev + offsets[i] elements (3*ny*nx
+ * elements, the layout above; the states must not overlap), parameters p[i]
+ * (every SO form without a y derivative: none or gamma p_x Sigma_x).  n is
+ * at most 65536.  The arrays are copied; the pool stays owned by the caller
+ * and must outlive the batch.  Creation synchronises the stream. */
 int ssgp_create_batch(int n, const int *nx, const int *ny, const double *dx,
                       const ssgp_params *p, int dtype, void *pool_dev,
                       const long long *offsets, void *hip_stream, ssgp_batch *out);
 
-/* nsteps imaginary-time steps of every grid of the batch, as one persistent
- * kernel launch (replayed from a HIP graph) with device-wide barriers between
- * the x and y sweeps. */
+/* nsteps imaginary-time steps of every grid of the batch; each grid is
+ * normalised on return.  The steps run as graphs of 2^i steps (HIP graphs,
+ * captured on first use) of the batch's launch shape: one persistent kernel
+ * with device-wide barriers between the x and y sweeps, or one kernel launch
+ * per sweep over all grids.  The first call times every shape on a scratch
+ * copy of the pool (allocated for the duration of the tuning) unless
+ * ssgp_batch_set_shape fixed one; results do not depend on the shape.  A
+ * barrier wait that times out ends the kernel (every workgroup leaves) and
+ * is reported by the next ssgp_batch_sync or ssgp_batch_observables. */
 int ssgp_batch_step_imag(ssgp_batch b, int nsteps);
 
-/* The same steps with one launch per sweep and instance (for comparison). */
+/* The same steps one grid at a time through the single-grid path (a launch
+ * per sweep and grid), for comparison.  Same result up to rounding order:
+ * the y lines are split into chunks differently. */
 int ssgp_batch_step_imag_serial(ssgp_batch b, int nsteps);
 
-/* Observables of every grid (out has n entries); synchronises the stream. */
+/* Launch shape of ssgp_batch_step_imag: k > 0 is the persistent kernel with
+ * k workgroups per compute unit (at most out[2] of ssgp_batch_info), -1 one
+ * kernel launch per sweep, 0 re-runs the autotuner at the next step call.
+ * Synchronises the stream when the shape changes. */
+int ssgp_batch_set_shape(ssgp_batch b, int shape);
+
+/* out[0..5] = {shape in use (0 before the first step call), persistent
+ * workgroups launched (0 for -1), maximum resident workgroups per compute
+ * unit, tuned microseconds per step of the shape in use (0 if it was set,
+ * not timed), x work items (rows), y work items (column tiles)}. */
+int ssgp_batch_info(ssgp_batch b, double *out);
+
+/* Synchronises the stream; SSGP_EDEVICE if a barrier of an earlier batched
+ * launch timed out (the batch state is then invalid; the flag is cleared). */
+int ssgp_batch_sync(ssgp_batch b);
+
+/* Observables of every grid (out has n entries); synchronises the stream
+ * and reports a barrier timeout as ssgp_batch_sync does. */
 int ssgp_batch_observables(ssgp_batch b, ssgp_obs *out);
 
 int ssgp_destroy_batch(ssgp_batch b);

@@ -79,6 +79,9 @@ def load():
                                ctypes.POINTER(G)], ci),
         "ssgp_batch_step_imag": ([G, ci], ci),
         "ssgp_batch_step_imag_serial": ([G, ci], ci),
+        "ssgp_batch_set_shape": ([G, ci], ci),
+        "ssgp_batch_info": ([G, ctypes.POINTER(cd)], ci),
+        "ssgp_batch_sync": ([G], ci),
         "ssgp_batch_observables": ([G, ctypes.POINTER(Obs)], ci),
         "ssgp_destroy_batch": ([G], ci),
         "ssgp_profile": ([G, ci, ci], ci),

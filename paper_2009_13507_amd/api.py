@@ -147,5 +147,100 @@ class Grid:
         return o.as_dict()
 
 
+class Batch:
+    """n independent 2D grids in one device pool, stepped together in
+    imaginary time (one persistent kernel, or one launch per sweep, replayed
+    from HIP graphs).  Instance i is the (3, ny_i, nx_i) view ``views[i]`` of
+    the pool."""
+
+    ALIGN = 32  # elements between instance starts are rounded up to this
+
+    def __init__(self, pool: torch.Tensor, shapes, dxs, params_list, offsets=None, stream=None):
+        lib = _lib.load()
+        if not pool.is_cuda or not pool.is_contiguous() or pool.dim() != 1:
+            raise ValueError("the pool must be a contiguous 1D device tensor")
+        n = len(shapes)
+        if not (len(dxs) == len(params_list) == n):
+            raise ValueError("shapes, dxs and params_list must have one entry per instance")
+        if offsets is None:
+            offsets = self.packed_offsets(shapes)
+        self.shapes = [(int(ny), int(nx)) for ny, nx in shapes]
+        self.offsets = [int(o) for o in offsets]
+        self.pool = pool
+        self.dtype = pool.dtype
+        nxs = (ctypes.c_int * n)(*[nx for _, nx in self.shapes])
+        nys = (ctypes.c_int * n)(*[ny for ny, _ in self.shapes])
+        dxa = (ctypes.c_double * n)(*[float(d) for d in dxs])
+        pa = (Params * n)(*params_list)
+        offa = (ctypes.c_longlong * n)(*self.offsets)
+        h = ctypes.c_void_p()
+        check(lib.ssgp_create_batch(n, nxs, nys, dxa, pa, _dtype_code(pool), _ptr(pool), offa,
+                                    _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.n = n
+
+    @classmethod
+    def packed_offsets(cls, shapes):
+        offs, at = [], 0
+        for ny, nx in shapes:
+            offs.append(at)
+            at += -(-3 * ny * nx // cls.ALIGN) * cls.ALIGN
+        return offs
+
+    @classmethod
+    def from_states(cls, states, dxs, params_list, dtype=torch.complex128, device="cuda:0", stream=None):
+        """Packs (3, ny, nx) states into a new pool on the device."""
+        shapes = [tuple(s.shape[1:]) for s in states]
+        offs = cls.packed_offsets(shapes)
+        total = offs[-1] + 3 * shapes[-1][0] * shapes[-1][1]
+        pool = torch.zeros(total, dtype=dtype, device=device)
+        b = cls(pool, shapes, dxs, params_list, offs, stream)
+        for v, s in zip(b.views(), states):
+            v.copy_(torch.as_tensor(s).to(device=device, dtype=dtype))
+        return b
+
+    def views(self):
+        return [self.pool[o:o + 3 * ny * nx].view(3, ny, nx) for o, (ny, nx) in zip(self.offsets, self.shapes)]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.ssgp_destroy_batch(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step_imag(self, n: int):
+        check(self._lib.ssgp_batch_step_imag(self._h, int(n)))
+
+    def step_imag_serial(self, n: int):
+        check(self._lib.ssgp_batch_step_imag_serial(self._h, int(n)))
+
+    def set_shape(self, shape: int):
+        """k > 0: persistent kernel, k workgroups per compute unit; -1: one
+        launch per sweep; 0: autotune at the next step call."""
+        check(self._lib.ssgp_batch_set_shape(self._h, int(shape)))
+
+    def info(self) -> dict:
+        out = (ctypes.c_double * 6)()
+        check(self._lib.ssgp_batch_info(self._h, out))
+        return {"shape": int(out[0]), "grid": int(out[1]), "max_per_cu": int(out[2]), "us_per_step": out[3],
+                "x_items": int(out[4]), "y_items": int(out[5])}
+
+    def sync(self):
+        check(self._lib.ssgp_batch_sync(self._h))
+
+    def observables(self):
+        obs = (Obs * self.n)()
+        rc = self._lib.ssgp_batch_observables(self._h, obs)
+        if rc != _lib.OK:
+            raise SSGPError(rc, self._lib.ssgp_last_error().decode())
+        return [o.as_dict() for o in obs]
+
+
 def version() -> str:
     return _lib.load().ssgp_version().decode()

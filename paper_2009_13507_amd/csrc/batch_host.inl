@@ -1,13 +1,384 @@
-// batch_host.inl -- batched API (included by ssgp.hip).
-struct ssgp_batch_s {
-    int n = 0;
+// batch_host.inl -- batched imaginary-time stepping (included by ssgp.hip).
+//
+// A batch keeps one single-grid object per instance over its slice of the
+// pool (source of the x-line tables, the one-instance-at-a-time path and the
+// observables), the descriptor table and item lists of the batched kernels,
+// and the HIP graphs of the chosen launch shape.
+//
+// Launch shapes: k > 0 is the persistent kernel with k workgroups per
+// compute unit (every workgroup resident, device-wide barriers between the
+// phases); -1 is one kernel launch per phase.  All shapes run the same item
+// functions, so the results do not depend on the shape.  The autotuner
+// times every shape on a scratch copy of the pool at the first step call and
+// keeps the fastest.  A run of n steps is replayed as graphs of 2^i steps
+// (binary decomposition of n); a graph ends with the RENORM scale of its last
+// step, which gives bitwise the same state as one longer run, since the next
+// step would apply the same rounded product first.
+
+static constexpr long long BATCH_SPIN_LIMIT = 1LL << 21;  // a second or more per barrier wait
+static constexpr int BATCH_LOG2_PERSISTENT = 12;          // persistent graphs of up to 4096 steps
+static constexpr int BATCH_LOG2_PHASED = 6;               // phase-launch graphs of up to 64 steps
+static constexpr int BATCH_MAX_INSTANCES = 1 << 16;
+
+template <typename R> struct BatchTabs {
+    DevBuf inst;                // BatchInst<R>[n]
+    std::vector<CNDev<R>> ly;   // y-line tables in the batched chunking
 };
-extern "C" int ssgp_create_batch(int, const int *, const int *, const double *, const ssgp_params *, int, void *,
-                                 const long long *, void *, ssgp_batch *out) {
-    if (out) *out = nullptr;
-    return fail(SSGP_EINVAL, "batched mode not built yet");
+
+struct ssgp_batch_s {
+    int n = 0, dtype = SSGP_C128, ncu = 1;
+    void *pool = nullptr;
+    size_t pool_bytes = 0;      // extent of the pool the instances use
+    hipStream_t stream = nullptr, cap = nullptr;
+    std::vector<ssgp_grid> grids;
+    int nrows = 0, nyitems = 0, ntiles = 0;
+    DevBuf xitems, yitems, partials, renorm, counters, bar;
+    BatchTabs<double> t64;
+    BatchTabs<float> t32;
+    int occ = 0;                // resident persistent workgroups per compute unit
+    int shape = 0;              // 0: choose at the next step call
+    double shape_us = 0.0;      // measured microseconds per step of the shape in use (0 if not timed)
+    std::vector<hipGraphExec_t> graphs;  // [log2 steps] for the shape in use
+    void drop_graphs() {
+        for (hipGraphExec_t &g : graphs)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    }
+    ~ssgp_batch_s() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        drop_graphs();
+        for (ssgp_grid g : grids) ssgp_destroy(g);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+template <typename R> static BatchTabs<R> &btabs(ssgp_batch b);
+template <> BatchTabs<double> &btabs<double>(ssgp_batch b) { return b->t64; }
+template <> BatchTabs<float> &btabs<float>(ssgp_batch b) { return b->t32; }
+
+// y chunk: smallest power of two with BATCH_THREADS/TX chunks covering ny
+template <typename R> static int batch_y_chunk(int ny) {
+    const int P = BATCH_THREADS / BatchTX<R>::v;
+    return pow2_at_least((ny + P - 1) / P);
 }
-extern "C" int ssgp_batch_step_imag(ssgp_batch, int) { return fail(SSGP_EINVAL, "batched mode not built yet"); }
-extern "C" int ssgp_batch_step_imag_serial(ssgp_batch, int) { return fail(SSGP_EINVAL, "batched mode not built yet"); }
-extern "C" int ssgp_batch_observables(ssgp_batch, ssgp_obs *) { return fail(SSGP_EINVAL, "batched mode not built yet"); }
-extern "C" int ssgp_destroy_batch(ssgp_batch b) { delete b; return SSGP_OK; }
+
+template <typename R> static int batch_build(ssgp_batch b, const long long *offsets) {
+    constexpr int TX = BatchTX<R>::v;
+    const int P = BATCH_THREADS / TX;
+    int maxlv = 0;
+    while ((TX << maxlv) < 64) ++maxlv;
+    BatchTabs<R> &T = btabs<R>(b);
+    T.ly.resize(b->n);
+    std::vector<BatchInst<R>> host(b->n);
+    int tile_base = 0;
+    for (int i = 0; i < b->n; ++i) {
+        ssgp_grid g = b->grids[i];
+        SSGP_TRY(build_tables<R>(g, MODE_IMAG));
+        const XArgs<R> xa = x_args<R>(g, MODE_IMAG, nullptr, nullptr, g->p.omega, nullptr);
+        const int Ly = batch_y_chunk<R>(g->ny);
+        SSGP_TRY(upload_cn<R>(T.ly[i], cn_tables(g->ny, g->dy, cn_s(MODE_IMAG, g->p.dt), Ly, P, maxlv), g->ny, Ly, P,
+                              b->stream));
+        BatchInst<R> &I = host[i];
+        I = BatchInst<R>{};
+        I.off = offsets[i];
+        I.nx = g->nx;
+        I.ny = g->ny;
+        I.Lx = x_chunk(g->nx);
+        I.Ly = Ly;
+        I.ntiles = (g->nx + TX - 1) / TX;
+        I.tile_base = tile_base;
+        tile_base += I.ntiles;
+        I.dx = xa.dx;
+        I.dy = xa.dy;
+        I.x0 = xa.x0;
+        I.y0 = xa.y0;
+        I.m = xa.m;
+        I.lx = xa.cx_;
+        I.ly = T.ly[i].coef();
+        I.rdx = xa.rdiag;
+        I.rox = xa.roff;
+        I.rdy = T.ly[i].rdiag;
+        I.roy = T.ly[i].roff;
+        for (int q = 0; q < 9; ++q) I.qx[q] = xa.qx[q];
+        I.qxmask = xa.qxmask;
+        I.sp = renorm_spec(*g);
+    }
+    b->ntiles = tile_base;
+    SSGP_TRY(T.inst.ensure(sizeof(BatchInst<R>) * b->n));
+    HIP_TRY(hipMemcpyAsync(T.inst.p, host.data(), sizeof(BatchInst<R>) * b->n, hipMemcpyHostToDevice, b->stream));
+
+    // work items, the costliest first (rows by nx, tiles by ny), so that the
+    // round-robin assignment over the workgroups ends evenly
+    std::vector<int> order(b->n);
+    for (int i = 0; i < b->n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return host[u].nx > host[v].nx; });
+    std::vector<int> xi;
+    for (int i : order)
+        for (int r = 0; r < host[i].ny; ++r) xi.push_back((i << 10) | r);
+    std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return host[u].ny > host[v].ny; });
+    std::vector<int> yi;
+    for (int i : order)
+        for (int j = 0; j < 3; ++j)
+            for (int t = 0; t < host[i].ntiles; ++t) yi.push_back((i << 8) | (j << 6) | t);
+    b->nrows = (int)xi.size();
+    b->nyitems = (int)yi.size();
+    SSGP_TRY(b->xitems.ensure(sizeof(int) * xi.size()));
+    SSGP_TRY(b->yitems.ensure(sizeof(int) * yi.size()));
+    HIP_TRY(hipMemcpyAsync(b->xitems.p, xi.data(), sizeof(int) * xi.size(), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->yitems.p, yi.data(), sizeof(int) * yi.size(), hipMemcpyHostToDevice, b->stream));
+    SSGP_TRY(b->partials.ensure(sizeof(double) * 3 * b->ntiles));
+    SSGP_TRY(b->renorm.ensure(sizeof(double) * 8 * b->n));
+    SSGP_TRY(b->counters.ensure(sizeof(unsigned) * b->n));
+    SSGP_TRY(b->bar.ensure(sizeof(unsigned) * 4));
+    HIP_TRY(hipMemsetAsync(b->renorm.p, 0, sizeof(double) * 8 * b->n, b->stream));
+    HIP_TRY(hipMemsetAsync(b->counters.p, 0, sizeof(unsigned) * b->n, b->stream));
+    HIP_TRY(hipMemsetAsync(b->bar.p, 0, sizeof(unsigned) * 4, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));  // the host vectors above go out of scope
+    HIP_TRY(batch_occupancy<R>(&b->occ));
+    if (b->occ < 1) return fail(SSGP_EDEVICE, "the batched kernel does not fit on a compute unit");
+    return SSGP_OK;
+}
+
+template <typename R> static BatchArgs<R> batch_args(ssgp_batch b, void *pool, int nsteps) {
+    BatchArgs<R> a{};
+    a.pool = static_cast<cx<R> *>(pool);
+    a.inst = btabs<R>(b).inst.template as<BatchInst<R>>();
+    a.x_items = b->xitems.as<int>();
+    a.y_items = b->yitems.as<int>();
+    a.nrows = b->nrows;
+    a.nyitems = b->nyitems;
+    a.partials = b->partials.as<double>();
+    a.renorm = b->renorm.as<double>();
+    a.counters = b->counters.as<unsigned>();
+    a.bar = b->bar.as<unsigned>();
+    a.nsteps = nsteps;
+    a.spin_limit = BATCH_SPIN_LIMIT;
+    return a;
+}
+
+// Enqueues nsteps steps of the pool at `pool` in launch shape `shape`.
+template <typename R> static int batch_enqueue(ssgp_batch b, hipStream_t st, void *pool, int nsteps, int shape) {
+    if (nsteps <= 0) return SSGP_OK;
+    const BatchArgs<R> a = batch_args<R>(b, pool, nsteps);
+    LAUNCH_TRY(launch_batch_reset(st, b->bar.as<unsigned>(), b->counters.as<unsigned>(), b->n));
+    if (shape > 0) {
+        LAUNCH_TRY(launch_batch_persistent<R>(st, a, shape * b->ncu));
+    } else {
+        for (int s = 0; s < nsteps; ++s) {
+            LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_X, s > 0 ? 1 : 0));
+            LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_Y, 0));
+        }
+        LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_SCALE, 0));
+    }
+    return SSGP_OK;
+}
+
+// Times every launch shape on a scratch copy of the pool; keeps the fastest.
+template <typename R> static int batch_tune(ssgp_batch b) {
+    DevBuf scratch;
+    SSGP_TRY(scratch.ensure(b->pool_bytes));
+    HIP_TRY(hipMemcpyAsync(scratch.p, b->pool, b->pool_bytes, hipMemcpyDeviceToDevice, b->stream));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SSGP_EDEVICE, "hipEventCreate failed");
+    }
+    std::vector<int> shapes = {-1};
+    for (int k = 1; k <= b->occ; ++k) shapes.push_back(k);
+    const int steps = 4, reps = 3;
+    int best = 0;
+    double best_us = 0.0;
+    int rc = SSGP_OK;
+    for (int shape : shapes) {
+        double t_min = 1e300;
+        for (int r = 0; r <= reps && rc == SSGP_OK; ++r) {  // r = 0 warms up
+            rc = batch_enqueue<R>(b, b->stream, scratch.p, steps, shape);
+            if (rc != SSGP_OK) break;
+            if (hipEventRecord(e0, b->stream) != hipSuccess) rc = fail(SSGP_EDEVICE, "hipEventRecord failed");
+            if (rc == SSGP_OK) rc = batch_enqueue<R>(b, b->stream, scratch.p, steps, shape);
+            if (rc == SSGP_OK && hipEventRecord(e1, b->stream) != hipSuccess)
+                rc = fail(SSGP_EDEVICE, "hipEventRecord failed");
+            if (rc == SSGP_OK && hipEventSynchronize(e1) != hipSuccess)
+                rc = fail(SSGP_EDEVICE, "hipEventSynchronize failed");
+            float ms = 0.f;
+            if (rc == SSGP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = fail(SSGP_EDEVICE, "hipEventElapsedTime failed");
+            if (rc == SSGP_OK && r > 0) t_min = std::min(t_min, 1e3 * ms / steps);
+        }
+        if (rc != SSGP_OK) break;
+        if (best == 0 || t_min < best_us) {
+            best = shape;
+            best_us = t_min;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    SSGP_TRY(rc);
+    unsigned flag[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(flag, b->bar.p, sizeof flag, hipMemcpyDeviceToHost));
+    if (flag[2] != 0u || flag[3] != 0u)
+        return fail(SSGP_EDEVICE, "a device-wide barrier of the batched kernel timed out while tuning");
+    b->shape = best;
+    b->shape_us = best_us;
+    return SSGP_OK;
+}
+
+template <typename R> static int batch_graph(ssgp_batch b, int lg, hipGraphExec_t *out) {
+    if ((int)b->graphs.size() <= lg) b->graphs.resize(lg + 1, nullptr);
+    if (!b->graphs[lg]) {
+        HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        const int rc = batch_enqueue<R>(b, b->cap, b->pool, 1 << lg, b->shape);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap, &graph);
+        SSGP_TRY(rc);
+        if (e != hipSuccess) return fail(SSGP_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) return fail(SSGP_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e2));
+        b->graphs[lg] = exec;
+    }
+    *out = b->graphs[lg];
+    return SSGP_OK;
+}
+
+template <typename R> static int batch_step_t(ssgp_batch b, int nsteps) {
+    if (nsteps == 0) return SSGP_OK;
+    if (b->shape == 0) SSGP_TRY(batch_tune<R>(b));
+    const int maxlg = b->shape > 0 ? BATCH_LOG2_PERSISTENT : BATCH_LOG2_PHASED;
+    int rem = nsteps;
+    for (int lg = maxlg; lg >= 0; --lg) {
+        while (rem >= (1 << lg)) {
+            hipGraphExec_t g = nullptr;
+            SSGP_TRY(batch_graph<R>(b, lg, &g));
+            HIP_TRY(hipGraphLaunch(g, b->stream));
+            rem -= 1 << lg;
+        }
+    }
+    return SSGP_OK;
+}
+
+// ---------------------------------------------------------------- ABI ---
+extern "C" int ssgp_create_batch(int n, const int *nx, const int *ny, const double *dx, const ssgp_params *p,
+                                 int dtype, void *pool_dev, const long long *offsets, void *hip_stream,
+                                 ssgp_batch *out) {
+    if (!out) return fail(SSGP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > BATCH_MAX_INSTANCES) return fail(SSGP_EINVAL, "n must be in [1, %d]", BATCH_MAX_INSTANCES);
+    if (!nx || !ny || !dx || !p || !offsets || !pool_dev) return fail(SSGP_EINVAL, "NULL argument");
+    if (dtype != SSGP_C128 && dtype != SSGP_C64) return fail(SSGP_EINVAL, "unknown dtype %d", dtype);
+    std::vector<std::pair<long long, long long>> spans(n);
+    for (int i = 0; i < n; ++i) {
+        if (nx[i] < 1 || nx[i] > BATCH_MAX_N || ny[i] < 1 || ny[i] > BATCH_MAX_N)
+            return fail(SSGP_EINVAL, "instance %d: nx and ny must be in [1, %d]", i, BATCH_MAX_N);
+        if (!(dx[i] > 0) || !std::isfinite(dx[i])) return fail(SSGP_EINVAL, "instance %d: dx must be positive", i);
+        if (offsets[i] < 0) return fail(SSGP_EINVAL, "instance %d: negative offset", i);
+        if (so_has_y(p[i].so) && p[i].gamma != 0.0)
+            return fail(SSGP_EINVAL, "instance %d: y-dependent SO forms are not supported in batched mode", i);
+        spans[i] = {offsets[i], offsets[i] + 3LL * nx[i] * ny[i]};
+    }
+    std::sort(spans.begin(), spans.end());
+    for (int i = 1; i < n; ++i)
+        if (spans[i].first < spans[i - 1].second) return fail(SSGP_EINVAL, "instance states overlap in the pool");
+    ssgp_batch b = new (std::nothrow) ssgp_batch_s();
+    if (!b) return fail(SSGP_ENOMEM, "host allocation failed");
+    b->n = n;
+    b->dtype = dtype;
+    b->pool = pool_dev;
+    b->pool_bytes = (size_t)spans[n - 1].second * elem_bytes(dtype);
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    int rc = SSGP_OK;
+    for (int i = 0; i < n && rc == SSGP_OK; ++i) {
+        ssgp_grid g = nullptr;
+        rc = ssgp_create_grid(2, nx[i], ny[i], dx[i], dx[i], dtype,
+                              static_cast<char *>(pool_dev) + offsets[i] * (long long)elem_bytes(dtype), hip_stream, &g);
+        if (rc == SSGP_OK) {
+            b->grids.push_back(g);
+            rc = ssgp_set_params(g, &p[i]);
+            if (rc != SSGP_OK) {
+                const std::string m = g_err;
+                rc = fail(rc, "instance %d: %s", i, m.c_str());
+            }
+        }
+    }
+    if (rc == SSGP_OK) b->ncu = b->grids[0]->ncu;
+    if (rc == SSGP_OK && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(SSGP_EDEVICE, "hipStreamCreateWithFlags failed");
+    if (rc == SSGP_OK) rc = dtype == SSGP_C128 ? batch_build<double>(b, offsets) : batch_build<float>(b, offsets);
+    if (rc != SSGP_OK) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_batch_step_imag(ssgp_batch b, int nsteps) {
+    if (!b) return fail(SSGP_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(SSGP_EINVAL, "nsteps < 0");
+    return b->dtype == SSGP_C128 ? batch_step_t<double>(b, nsteps) : batch_step_t<float>(b, nsteps);
+}
+
+extern "C" int ssgp_batch_step_imag_serial(ssgp_batch b, int nsteps) {
+    if (!b) return fail(SSGP_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(SSGP_EINVAL, "nsteps < 0");
+    for (ssgp_grid g : b->grids) SSGP_TRY(ssgp_step_imag(g, nsteps));
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_batch_set_shape(ssgp_batch b, int shape) {
+    if (!b) return fail(SSGP_EINVAL, "batch is NULL");
+    if (shape < -1 || shape > b->occ)
+        return fail(SSGP_EINVAL, "shape must be -1, 0 or a workgroup count in [1, %d] per compute unit", b->occ);
+    if (shape != b->shape) {
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        b->drop_graphs();
+        b->shape = shape;
+        b->shape_us = 0.0;
+    }
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_batch_info(ssgp_batch b, double *out) {
+    if (!b || !out) return fail(SSGP_EINVAL, "NULL argument");
+    out[0] = b->shape;
+    out[1] = b->shape > 0 ? (double)b->shape * b->ncu : 0.0;
+    out[2] = b->occ;
+    out[3] = b->shape_us;
+    out[4] = b->nrows;
+    out[5] = b->nyitems;
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_batch_sync(ssgp_batch b) {
+    if (!b) return fail(SSGP_EINVAL, "batch is NULL");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    unsigned flag[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(flag, b->bar.p, sizeof flag, hipMemcpyDeviceToHost));
+    if (flag[2] != 0u || flag[3] != 0u) {
+        HIP_TRY(hipMemsetAsync(b->bar.p, 0, sizeof(unsigned) * 4, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        return fail(SSGP_EDEVICE, "a device-wide barrier of the batched kernel timed out; the batch state is invalid");
+    }
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_batch_observables(ssgp_batch b, ssgp_obs *out) {
+    if (!b || !out) return fail(SSGP_EINVAL, "NULL argument");
+    SSGP_TRY(ssgp_batch_sync(b));
+    int rc = SSGP_OK;
+    for (int i = 0; i < b->n; ++i) {
+        const int r = ssgp_observables(b->grids[i], &out[i]);
+        if (r == SSGP_ENONFINITE && rc == SSGP_OK) rc = fail(r, "instance %d holds NaN or Inf", i);
+        else if (r != SSGP_OK && r != SSGP_ENONFINITE) return r;
+    }
+    return rc;
+}
+
+extern "C" int ssgp_destroy_batch(ssgp_batch b) {
+    delete b;
+    return SSGP_OK;
+}

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "adjoint_kernels.hpp"
+#include "batch_kernels.hpp"
 #include "obs_kernels.hpp"
 #include "step_kernels.hpp"
 
@@ -33,6 +34,13 @@ template <typename R> hipError_t launch_obs(const Launch &c, const ObsArgs<R> &a
 hipError_t launch_renorm_finalize(const Launch &c, const double *partials, int ntiles, RenormSpec sp, double *out);
 hipError_t launch_obs_finalize(const Launch &c, const double *partials, int nblocks, double *out);
 hipError_t launch_omega_accumulate(const Launch &c, const double *partials, int nrows, double *acc, int seg);
+
+// batched imaginary-time step
+enum { BATCH_PHASE_X = 0, BATCH_PHASE_Y = 1, BATCH_PHASE_SCALE = 2 };
+template <typename R> hipError_t batch_occupancy(int *per_cu);
+template <typename R> hipError_t launch_batch_persistent(hipStream_t s, const BatchArgs<R> &a, int grid);
+template <typename R> hipError_t launch_batch_phase(hipStream_t s, const BatchArgs<R> &a, int phase, int apply_renorm);
+hipError_t launch_batch_reset(hipStream_t s, unsigned *bar, unsigned *counters, int n);
 
 // chunk lengths with compiled kernels (row kernels: one 64-lane wavefront
 // per line, so nx <= 64 L <= 2048)

@@ -173,6 +173,12 @@ def batch_draw(n: int = 64, seed: int = 1):
     return out
 
 
+def batch_initial(w: Workload, phases):
+    """Initial state of one batched instance: the Gaussian trial state of the
+    2D imaginary-time workload with the instance's own component phases."""
+    return gaussian(2, w.nx, w.ny, w.dx, w.dy, phases=tuple(phases))
+
+
 def omega_schedule(nseg: int = 100, seed: int = 2):
     """Piecewise-constant Rabi control: one Omega per segment, U[0, 0.3]."""
     return np.random.default_rng(seed).uniform(0.0, 0.3, nseg)

@@ -63,3 +63,40 @@ def test_null_arguments(lib):
     assert lib.ssgp_step_imag(None, 1) == _lib.EINVAL
     assert lib.ssgp_set_params(None, None) == _lib.EINVAL
     assert lib.ssgp_destroy(None) == _lib.OK
+
+
+def _batch_args(n, nx, ny, offsets, so=1):
+    ci, cd, cll = ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    prm = (_lib.Params * n)(*[_lib.Params(2.0, -0.1, 0.5, 0.1, 1.0, 1e-3, 0.0, so, 0) for _ in range(n)])
+    return ((ci * n)(*nx), (ci * n)(*ny), (cd * n)(*([0.1] * n)), prm, (cll * n)(*offsets))
+
+
+@pytest.mark.parametrize("n,nx,ny,offsets,so,fragment", [
+    (2, [16, 16], [16, 16], [0, 3 * 256 - 1], 1, b"overlap"),
+    (2, [16, 16], [16, 16], [3 * 256, 0], 0, b"ok"),
+    (1, [513], [16], [0], 1, b"512"),
+    (1, [16], [0], [0], 1, b"512"),
+    (1, [16], [16], [-1], 1, b"offset"),
+    (1, [16], [16], [0], 4, b"y-dependent"),
+])
+def test_create_batch_rejects_bad_arguments(lib, n, nx, ny, offsets, so, fragment):
+    if fragment == b"ok":
+        pytest.skip("valid arguments reach the device")
+    nxa, nya, dxa, prm, offa = _batch_args(n, nx, ny, offsets, so)
+    h = ctypes.c_void_p(123)
+    rc = lib.ssgp_create_batch(n, nxa, nya, dxa, prm, 0, ctypes.c_void_p(1), offa, None, ctypes.byref(h))
+    assert rc == _lib.EINVAL
+    assert h.value is None
+    assert fragment in lib.ssgp_last_error()
+
+
+def test_batch_null_arguments(lib):
+    nxa, nya, dxa, prm, offa = _batch_args(1, [8], [8], [0])
+    h = ctypes.c_void_p()
+    assert lib.ssgp_create_batch(0, nxa, nya, dxa, prm, 0, ctypes.c_void_p(1), offa, None,
+                                 ctypes.byref(h)) == _lib.EINVAL
+    assert lib.ssgp_create_batch(1, nxa, nya, dxa, prm, 0, None, offa, None, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.ssgp_batch_step_imag(None, 1) == _lib.EINVAL
+    assert lib.ssgp_batch_sync(None) == _lib.EINVAL
+    assert lib.ssgp_batch_set_shape(None, 1) == _lib.EINVAL
+    assert lib.ssgp_destroy_batch(None) == _lib.OK

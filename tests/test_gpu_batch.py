@@ -1,0 +1,224 @@
+"""Batched imaginary-time stepping on the GPU, through the C ABI.
+
+Every instance of a ragged batch against the CPU oracle (FP64, relative L2
+<= 1e-10), every launch shape bitwise equal to every other, a run split into
+several calls bitwise equal to one call, the batched path against the
+one-grid-at-a-time path (<= 1e-12: the y lines are chunked differently),
+per-instance observables against a single grid's, and the 64-instance
+workload in complex128 and complex64."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2009_13507_amd import api  # noqa: E402
+from paper_2009_13507_amd import workloads as W  # noqa: E402
+
+TOL = 1e-10
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# (ny, nx, dx, c0, c2, gamma, omega, so): ragged shapes with tails in both
+# directions, single rows and columns, the largest size, and one instance on
+# the fixed-magnetisation RENORM rule (Omega = 0, no SO)
+RAGGED = [
+    (33, 40, 0.30, 3.0, -0.7, 0.6, 0.25, api.SO_PX_SX),
+    (64, 64, 0.25, 1.0, 0.3, 0.0, 0.10, api.SO_NONE),
+    (70, 130, 0.22, 4.0, -0.2, 0.9, 0.05, api.SO_PX_SX),
+    (200, 17, 0.20, 2.0, 0.1, 0.4, 0.30, api.SO_PX_SX),
+    (48, 512, 0.10, 2.5, -0.4, 0.7, 0.20, api.SO_PX_SX),
+    (512, 24, 0.10, 1.5, 0.2, 0.3, 0.15, api.SO_PX_SX),
+    (1, 9, 0.35, 2.0, -0.3, 0.5, 0.20, api.SO_PX_SX),
+    (7, 1, 0.35, 2.0, -0.3, 0.0, 0.20, api.SO_NONE),
+    (96, 80, 0.25, 2.0, -0.5, 0.0, 0.00, api.SO_NONE),
+]
+DT = 2e-3
+
+
+def ragged_states(seed=0):
+    out = []
+    for k, (ny, nx, dx, *_rest) in enumerate(RAGGED):
+        base = W.gaussian(2, nx, ny, dx, dx, phases=(0.3 + k, 1.1, 2.0 - k), width=1.5)
+        out.append(base * (1 + W.random_state(base.shape, seed + k, 0.05)))
+    return out
+
+
+def ragged_params():
+    return [api.params(c0=c0, c2=c2, gamma=g, omega=om, dt=DT, so=so) for (_, _, _, c0, c2, g, om, so) in RAGGED]
+
+
+def make_ragged(dtype=torch.complex128):
+    return api.Batch.from_states(ragged_states(), [r[2] for r in RAGGED], ragged_params(), dtype=dtype)
+
+
+def snapshot(b):
+    torch.cuda.synchronize()
+    return [v.cpu().to(torch.complex128).numpy() for v in b.views()]
+
+
+def oracle_run(k, psi0, nsteps):
+    ny, nx, dx, c0, c2, g, om, so = RAGGED[k]
+    cfg = oracle.Cfg(dim=2, nx=nx, ny=ny, dx=dx, dy=dx, c0=c0, c2=c2, gamma=g, omega=om, dt=DT, imag=True, so=so)
+    return oracle.step(cfg, psi0, nsteps)
+
+
+@pytest.mark.parametrize("shape", [-1, 1, "max"])
+def test_batch_matches_oracle(shape):
+    b = make_ragged()
+    b.set_shape(b.info()["max_per_cu"] if shape == "max" else shape)
+    b.step_imag(13)  # graphs of 8, 4 and 1 steps
+    b.sync()
+    got = snapshot(b)
+    for k, psi0 in enumerate(ragged_states()):
+        assert rel(got[k], oracle_run(k, psi0, 13)) < TOL, k
+    b.close()
+
+
+def test_every_shape_gives_identical_bits():
+    ref = None
+    b0 = make_ragged()
+    shapes = [-1] + list(range(1, b0.info()["max_per_cu"] + 1))
+    b0.close()
+    for shape in shapes:
+        b = make_ragged()
+        b.set_shape(shape)
+        b.step_imag(9)
+        b.sync()
+        got = snapshot(b)
+        if ref is None:
+            ref = got
+        else:
+            for k in range(len(RAGGED)):
+                assert np.array_equal(got[k], ref[k]), (shape, k)
+        b.close()
+
+
+def test_split_runs_give_identical_bits():
+    a = make_ragged()
+    a.set_shape(1)
+    a.step_imag(11)
+    b = make_ragged()
+    b.set_shape(1)
+    b.step_imag(3)
+    b.step_imag(6)
+    b.step_imag(2)
+    ra, rb = snapshot(a), snapshot(b)
+    for k in range(len(RAGGED)):
+        assert np.array_equal(ra[k], rb[k]), k
+
+
+def test_autotuner_picks_a_timed_shape():
+    b = make_ragged()
+    assert b.info()["shape"] == 0
+    b.step_imag(5)
+    b.sync()
+    info = b.info()
+    assert info["shape"] == -1 or 1 <= info["shape"] <= info["max_per_cu"]
+    assert info["us_per_step"] > 0
+    ref = make_ragged()
+    ref.set_shape(-1)
+    ref.step_imag(5)
+    for x, y in zip(snapshot(b), snapshot(ref)):
+        assert np.array_equal(x, y)
+
+
+def test_batched_matches_serial_path():
+    a = make_ragged()
+    a.set_shape(-1)
+    a.step_imag(40)
+    s = make_ragged()
+    s.step_imag_serial(40)
+    for k, (x, y) in enumerate(zip(snapshot(a), snapshot(s))):
+        assert rel(x, y) < 1e-12, k
+
+
+def test_observables_match_single_grids():
+    b = make_ragged()
+    b.set_shape(1)
+    b.step_imag(6)
+    obs = b.observables()
+    for k, v in enumerate(b.views()):
+        ny, nx, dx, c0, c2, g, om, so = RAGGED[k]
+        t = v.clone()
+        grid = api.Grid(t, dx, dx)
+        grid.set_params(c0=c0, c2=c2, gamma=g, omega=om, dt=DT, so=so)
+        ref = grid.observables()
+        grid.close()
+        for key in ("N", "M", "E", "rms"):
+            assert obs[k][key] == pytest.approx(ref[key], rel=1e-13, abs=1e-14), (k, key)
+        assert obs[k]["N"] == pytest.approx(1.0, abs=1e-12)
+
+
+def test_zero_steps_leave_the_pool_unchanged():
+    b = make_ragged()
+    before = snapshot(b)
+    b.step_imag(0)
+    b.step_imag_serial(0)
+    for x, y in zip(before, snapshot(b)):
+        assert np.array_equal(x, y)
+
+
+def test_bad_shape_is_rejected():
+    b = make_ragged()
+    with pytest.raises(api.SSGPError):
+        b.set_shape(b.info()["max_per_cu"] + 1)
+    with pytest.raises(api.SSGPError):
+        b.set_shape(-2)
+
+
+# ------------------------------------------------ the 64-instance workload --
+def c4_batch(dtype):
+    draw = W.batch_draw(64, seed=1)
+    states = [W.batch_initial(w, ph) for w, ph in draw]
+    prm = [api.params(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, dt=w.dt, so=w.so) for w, _ in draw]
+    return draw, states, api.Batch.from_states(states, [w.dx for w, _ in draw], prm, dtype=dtype)
+
+
+def test_c4_draw_is_the_stated_mix():
+    draw = W.batch_draw(64, seed=1)
+    sizes = [w.nx for w, _ in draw]
+    assert [sizes.count(n) for n in W.BATCH_SIZES] == [13, 14, 15, 8, 14]
+    assert sum(n * n for n in sizes) == 6561792
+
+
+def test_c4_batched_against_serial_and_oracle():
+    draw, states, b = c4_batch(torch.complex128)
+    b.step_imag(20)
+    b.sync()
+    got = snapshot(b)
+    _, _, s = c4_batch(torch.complex128)
+    s.step_imag_serial(20)
+    ser = snapshot(s)
+    for k in range(64):
+        assert rel(got[k], ser[k]) < 1e-12, k
+    # one instance of each size against the oracle
+    seen = set()
+    for k, (w, _) in enumerate(draw):
+        if w.nx in seen:
+            continue
+        seen.add(w.nx)
+        cfg = oracle.Cfg(dim=2, nx=w.nx, ny=w.ny, dx=w.dx, dy=w.dy, c0=w.c0, c2=w.c2, gamma=w.gamma,
+                         omega=w.omega, dt=w.dt, imag=True, so=w.so)
+        assert rel(got[k], oracle.step(cfg, states[k], 20)) < TOL, k
+
+
+def test_c4_complex64_error_against_fp64():
+    """complex64 storage and arithmetic (coefficients rounded from FP64,
+    norms accumulated in FP64): relative L2 below 1e-5 and energy within
+    1e-5 of the FP64 batch after 50 steps."""
+    _, _, b64 = c4_batch(torch.complex128)
+    _, _, b32 = c4_batch(torch.complex64)
+    b64.step_imag(50)
+    b32.step_imag(50)
+    o64, o32 = b64.observables(), b32.observables()
+    r64, r32 = snapshot(b64), snapshot(b32)
+    for k in range(64):
+        assert rel(r32[k], r64[k]) < 1e-5, k
+        assert abs(o32[k]["E"] - o64[k]["E"]) < 1e-5 * max(1.0, abs(o64[k]["E"])), k
