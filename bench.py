@@ -113,6 +113,57 @@ def adjoint_ratio(reps: int = 2):
             "grad_omega_first": float(om.grad[0])}
 
 
+def batch_compare(steps: int = 200, warmup: int = 20):
+    """The 64-instance imaginary-time batch (sizes 128..512, seed-1 draw):
+    batched (autotuned launch shape, graph replay) against one grid at a
+    time, in complex128 and complex64, over a fixed window after warm-up;
+    plus the complex64 error against complex128 after the same steps."""
+    import numpy as np
+    import torch
+
+    from paper_2009_13507_amd import api
+    from paper_2009_13507_amd import workloads as W
+
+    draw = W.batch_draw(64, seed=1)
+    states = [W.batch_initial(w, ph) for w, ph in draw]
+    prm = [api.params(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, dt=w.dt, so=w.so) for w, _ in draw]
+    dxs = [w.dx for w, _ in draw]
+    npts = sum(w.nx * w.ny for w, _ in draw)
+    out = {"workload": "64 instances, N in {128,192,256,384,512}, seed 1, imaginary time, "
+                       "gamma p_x Sigma_x", "points": npts, "steps": steps}
+    finals = {}
+    for name, tdt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        b = api.Batch.from_states(states, dxs, prm, dtype=tdt)
+        b.step_imag(warmup)  # the first call runs the launch-shape tuner
+        b.sync()
+        t0 = time.perf_counter()
+        b.step_imag(steps)
+        b.sync()
+        t_b = time.perf_counter() - t0
+        b.step_imag_serial(warmup)
+        b.sync()
+        t0 = time.perf_counter()
+        b.step_imag_serial(steps)
+        b.sync()
+        t_s = time.perf_counter() - t0
+        info = b.info()
+        bpp = BYTES_PER_PT_PASS["f64" if name == "c128" else "f32"]
+        v_b, v_s = npts * steps / t_b, npts * steps / t_s
+        out[name] = {"batched_pt_steps_per_s": v_b, "serial_pt_steps_per_s": v_s, "speedup": v_b / v_s,
+                     "ms_per_step_batched": 1e3 * t_b / steps, "ms_per_step_serial": 1e3 * t_s / steps,
+                     "launch_shape": info["shape"], "persistent_workgroups": info["grid"],
+                     "tuned_us_per_step": info["us_per_step"],
+                     "hbm_frac_algorithmic": 2 * bpp * v_b / (HBM_PEAK_GBS * 1e9)}
+        finals[name] = ([v.cpu().to(torch.complex128).numpy() for v in b.views()],
+                        [o["E"] for o in b.observables()])
+        b.close()
+    errs = [float(np.linalg.norm(a - c) / np.linalg.norm(c)) for a, c in zip(finals["c64"][0], finals["c128"][0])]
+    dE = [abs(a - c) for a, c in zip(finals["c64"][1], finals["c128"][1])]
+    out["c64_vs_c128"] = {"max_rel_l2": max(errs), "max_abs_dE": max(dE),
+                          "after_steps": 2 * (steps + warmup)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +175,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint cost ratio")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-serial comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run torch copies of the state size (counter calibration)")
     args = ap.parse_args()
@@ -212,6 +264,8 @@ def main():
     }
     if not args.no_adjoint and args.dtype == "f64":
         line["adjoint_cost_ratio"] = adjoint_ratio()
+    if not args.no_batch:
+        line["batch_c4"] = batch_compare()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, psi0, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -32,7 +32,7 @@ struct ssgp_batch_s {
     hipStream_t stream = nullptr, cap = nullptr;
     std::vector<ssgp_grid> grids;
     int nrows = 0, nyitems = 0, ntiles = 0;
-    DevBuf xitems, yitems, partials, renorm, counters, bar;
+    DevBuf xitems, yitems, partials, renorm, bar;
     BatchTabs<double> t64;
     BatchTabs<float> t32;
     int occ = 0;                // resident persistent workgroups per compute unit
@@ -130,10 +130,8 @@ template <typename R> static int batch_build(ssgp_batch b, const long long *offs
     HIP_TRY(hipMemcpyAsync(b->yitems.p, yi.data(), sizeof(int) * yi.size(), hipMemcpyHostToDevice, b->stream));
     SSGP_TRY(b->partials.ensure(sizeof(double) * 3 * b->ntiles));
     SSGP_TRY(b->renorm.ensure(sizeof(double) * 8 * b->n));
-    SSGP_TRY(b->counters.ensure(sizeof(unsigned) * b->n));
     SSGP_TRY(b->bar.ensure(sizeof(unsigned) * 4));
     HIP_TRY(hipMemsetAsync(b->renorm.p, 0, sizeof(double) * 8 * b->n, b->stream));
-    HIP_TRY(hipMemsetAsync(b->counters.p, 0, sizeof(unsigned) * b->n, b->stream));
     HIP_TRY(hipMemsetAsync(b->bar.p, 0, sizeof(unsigned) * 4, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));  // the host vectors above go out of scope
     HIP_TRY(batch_occupancy<R>(&b->occ));
@@ -151,7 +149,7 @@ template <typename R> static BatchArgs<R> batch_args(ssgp_batch b, void *pool, i
     a.nyitems = b->nyitems;
     a.partials = b->partials.as<double>();
     a.renorm = b->renorm.as<double>();
-    a.counters = b->counters.as<unsigned>();
+    a.ninst = b->n;
     a.bar = b->bar.as<unsigned>();
     a.nsteps = nsteps;
     a.spin_limit = BATCH_SPIN_LIMIT;
@@ -162,13 +160,14 @@ template <typename R> static BatchArgs<R> batch_args(ssgp_batch b, void *pool, i
 template <typename R> static int batch_enqueue(ssgp_batch b, hipStream_t st, void *pool, int nsteps, int shape) {
     if (nsteps <= 0) return SSGP_OK;
     const BatchArgs<R> a = batch_args<R>(b, pool, nsteps);
-    LAUNCH_TRY(launch_batch_reset(st, b->bar.as<unsigned>(), b->counters.as<unsigned>(), b->n));
+    if (shape > 0) LAUNCH_TRY(launch_batch_reset(st, b->bar.as<unsigned>()));
     if (shape > 0) {
         LAUNCH_TRY(launch_batch_persistent<R>(st, a, shape * b->ncu));
     } else {
         for (int s = 0; s < nsteps; ++s) {
             LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_X, s > 0 ? 1 : 0));
             LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_Y, 0));
+            LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_R, 0));
         }
         LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_SCALE, 0));
     }

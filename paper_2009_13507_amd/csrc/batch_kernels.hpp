@@ -8,10 +8,10 @@
 //      coefficients; one item per 4-wavefront workgroup);
 //   Y phase, items (instance, component, tile of TX columns): the y-line
 //      solve (chunks in registers, chunk scans across the workgroup) and the
-//      tile's sum of |psi|^2.  The workgroup that completes the last tile of
-//      an instance (per-instance arrival counter) reduces the instance's
-//      tile sums in a fixed order and writes its RENORM factors (App. A,
-//      Eq. (DJ) or (DJ2)), which the next X phase applies.
+//      tile's sum of |psi|^2;
+//   R phase, items (instance): the fixed-order sum of the instance's tile
+//      sums and its RENORM factors (App. A, Eq. (DJ) or (DJ2)), which the
+//      next X phase applies.
 // After the last step a scale phase applies the last RENORM factors, so the
 // state is normalised on return.
 //
@@ -61,7 +61,7 @@ template <typename R> struct BatchArgs {
     int nrows, nyitems;
     double *partials;          // [total tiles][3] tile sums of |psi|^2
     double *renorm;            // [instances][8]: d[3], N[3], fallback
-    unsigned *counters;        // [instances] tile arrivals of the running Y phase
+    int ninst;
     unsigned *bar;             // [0] arrivals, [1] generation, [2] stop, [3] sticky timeout flag
     int nsteps;
     long long spin_limit;
@@ -106,7 +106,6 @@ template <typename R> struct BatchSmem {
     cx<R> edge[48];                          // x edge exchange: [2][4 waves][2 ends][3 comps]
     cx<R> scA[2][4][BatchTX<R>::v], scB[2][4][BatchTX<R>::v];
     double red[3][BATCH_THREADS];
-    int last;
 };
 
 // One x row of one instance (the single-grid x-pass algorithm, 4 waves).
@@ -347,16 +346,15 @@ __device__ __forceinline__ double batch_ytile(const BatchInst<R> &I, cx<R> *psi,
     return tot;
 }
 
-// Fixed-order sums of an instance's tile partials and its RENORM factors
-// (run by the workgroup that completed the instance's last tile).
-template <typename R>
-__device__ __forceinline__ void batch_renorm(const BatchArgs<R> &a, int inst, const BatchInst<R> &I,
-                                             BatchSmem<R> &S) {
+// R item: fixed-order sums of an instance's tile partials and its RENORM
+// factors.
+template <typename R> __device__ __forceinline__ void batch_renorm_item(const BatchArgs<R> &a, int inst,
+                                                                        BatchSmem<R> &S) {
+    const BatchInst<R> &I = a.inst[inst];
     const int t = threadIdx.x;
     for (int j = 0; j < 3; ++j) {
         double s = 0.0;
-        for (int q = t; q < I.ntiles; q += BATCH_THREADS)
-            s += coherent_load(a.partials + (long long)(I.tile_base + q) * 3 + j);
+        for (int q = t; q < I.ntiles; q += BATCH_THREADS) s += a.partials[(long long)(I.tile_base + q) * 3 + j];
         S.red[j][t] = s;
     }
     __syncthreads();
@@ -375,7 +373,6 @@ __device__ __forceinline__ void batch_renorm(const BatchArgs<R> &a, int inst, co
             o[3 + j] = N[j];
         }
         o[6] = fb;
-        __hip_atomic_store(a.counters + inst, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
 }
@@ -411,19 +408,7 @@ __device__ __forceinline__ void batch_y_item(const BatchArgs<R> &a, int q, Batch
     case 16: s = batch_ytile<R, 16>(I, psi, j, tile, S); break;
     default: s = batch_ytile<R, (BatchTX<R>::v == 8 ? 16 : 32)>(I, psi, j, tile, S); break;
     }
-    if (threadIdx.x == 0) {
-        a.partials[(long long)(I.tile_base + tile) * 3 + j] = s;
-        __threadfence();
-        const unsigned done =
-            __hip_atomic_fetch_add(a.counters + inst, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        S.last = done == (unsigned)(3 * I.ntiles - 1);
-    }
-    __syncthreads();
-    if (S.last) {
-        __threadfence();
-        batch_renorm(a, inst, I, S);
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) a.partials[(long long)(I.tile_base + tile) * 3 + j] = s;
 }
 
 template <typename R> __device__ __forceinline__ void batch_scale_item(const BatchArgs<R> &a, int q) {
@@ -449,6 +434,8 @@ __global__ void __launch_bounds__(BATCH_THREADS) batch_persistent_kernel(BatchAr
         if (!grid_sync(a.bar, a.spin_limit)) return;
         for (int q = blockIdx.x; q < a.nyitems; q += gridDim.x) batch_y_item(a, q, S);
         if (!grid_sync(a.bar, a.spin_limit)) return;
+        for (int q = blockIdx.x; q < a.ninst; q += gridDim.x) batch_renorm_item(a, q, S);
+        if (!grid_sync(a.bar, a.spin_limit)) return;
     }
     if (a.nsteps > 0)
         for (int q = blockIdx.x; q < a.nrows; q += gridDim.x) batch_scale_item(a, q);
@@ -465,6 +452,12 @@ template <typename R>
 __global__ void __launch_bounds__(BATCH_THREADS) batch_y_kernel(BatchArgs<R> a) {
     __shared__ BatchSmem<R> S;
     batch_y_item(a, blockIdx.x, S);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BATCH_THREADS) batch_renorm_kernel(BatchArgs<R> a) {
+    __shared__ BatchSmem<R> S;
+    batch_renorm_item(a, blockIdx.x, S);
 }
 
 template <typename R>

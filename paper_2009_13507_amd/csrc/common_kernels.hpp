@@ -70,11 +70,10 @@ __global__ void __launch_bounds__(256) omega_accumulate_kernel(const double *par
     if (threadIdx.x == 0) acc[seg] += red[0];
 }
 
-// Clears the batched step's barrier words and per-instance arrival counters
-// before a launch; a barrier timeout of the previous launch is kept in the
-// sticky flag bar[3] for the host.
-__global__ void __launch_bounds__(256) batch_reset_kernel(unsigned *bar, unsigned *counters, int n) {
-    for (int i = threadIdx.x; i < n; i += 256) counters[i] = 0u;
+// Clears the batched step's barrier words before a launch; a barrier
+// timeout of the previous launch is kept in the sticky flag bar[3] for the
+// host.
+__global__ void batch_reset_kernel(unsigned *bar) {
     if (threadIdx.x == 0) {
         if (bar[2] != 0u) bar[3] = 1u;
         bar[0] = 0u;

@@ -36,11 +36,11 @@ hipError_t launch_obs_finalize(const Launch &c, const double *partials, int nblo
 hipError_t launch_omega_accumulate(const Launch &c, const double *partials, int nrows, double *acc, int seg);
 
 // batched imaginary-time step
-enum { BATCH_PHASE_X = 0, BATCH_PHASE_Y = 1, BATCH_PHASE_SCALE = 2 };
+enum { BATCH_PHASE_X = 0, BATCH_PHASE_Y = 1, BATCH_PHASE_R = 2, BATCH_PHASE_SCALE = 3 };
 template <typename R> hipError_t batch_occupancy(int *per_cu);
 template <typename R> hipError_t launch_batch_persistent(hipStream_t s, const BatchArgs<R> &a, int grid);
 template <typename R> hipError_t launch_batch_phase(hipStream_t s, const BatchArgs<R> &a, int phase, int apply_renorm);
-hipError_t launch_batch_reset(hipStream_t s, unsigned *bar, unsigned *counters, int n);
+hipError_t launch_batch_reset(hipStream_t s, unsigned *bar);
 
 // chunk lengths with compiled kernels (row kernels: one 64-lane wavefront
 // per line, so nx <= 64 L <= 2048)

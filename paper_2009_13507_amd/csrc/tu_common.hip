@@ -19,8 +19,8 @@ hipError_t launch_omega_accumulate(const Launch &c, const double *partials, int 
     return hipGetLastError();
 }
 
-hipError_t launch_batch_reset(hipStream_t s, unsigned *bar, unsigned *counters, int n) {
-    batch_reset_kernel<<<1, 256, 0, s>>>(bar, counters, n);
+hipError_t launch_batch_reset(hipStream_t s, unsigned *bar) {
+    batch_reset_kernel<<<1, 64, 0, s>>>(bar);
     return hipGetLastError();
 }
 
