@@ -585,41 +585,26 @@ template <typename R> struct YArgs {
 constexpr int YPASS_MAX_THREADS = 512;
 constexpr int YPASS_MAX_WAVES = YPASS_MAX_THREADS / 64;
 
-// Workgroup: TX adjacent columns x P chunks of L rows (blockDim = TX * P);
-// lane tid holds column tid % TX, chunk tid / TX.  grid = (ceil(nx/TX), 3):
-// one workgroup per (tile, component).
-template <typename R, int L, int TX, bool GENERAL>
-__global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
-    __shared__ cx<R> scA[2][YPASS_MAX_WAVES][TX], scB[2][YPASS_MAX_WAVES][TX];
-    __shared__ double red[YPASS_MAX_WAVES];
+// Loads, right-hand side, elimination and chunk scans of one y-pass lane
+// (FULL: the lane holds L rows and its column is valid).
+template <typename R, int L, int TX, bool GENERAL, bool FULL>
+__device__ __forceinline__ void ypass_solve(const YArgs<R> &a, const cx<R> *col, int start, int len, int k, int c,
+                                            int lane, int wave, int nw, cx<R> (&r)[L],
+                                            cx<R> (&scA)[2][YPASS_MAX_WAVES][TX],
+                                            cx<R> (&scB)[2][YPASS_MAX_WAVES][TX]) {
     const int nx = a.nx, ny = a.ny;
-    // Workgroups are dispatched round-robin over the 8 XCDs; map them so that
-    // each XCD takes a contiguous range of tiles, keeping the two tiles that
-    // share a 128-byte line in one L2.
-    const int ntx = gridDim.x;
-    const int nb = ntx * gridDim.y;
-    const int b = blockIdx.x + ntx * blockIdx.y;
-    const int tile = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
-    const int j = tile / ntx, tx = tile % ntx;
-    const int tid = threadIdx.x, c = tid % TX, k = tid / TX;
-    const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    const int x = tx * TX + c;
-    const bool valid = x < nx;
-    const int start = k * L;
-    const int len = valid ? max(0, min(L, ny - start)) : 0;
-    cx<R> *col = a.psi + j * a.plane + (valid ? x : 0);
-
+    if (FULL) len = L;
     cx<R> f[L];
 #pragma unroll
-    for (int t = 0; t < L; ++t) f[t] = t < len ? col[(long long)(start + t) * nx] : czero<R>();
+    for (int t = 0; t < L; ++t) f[t] = (FULL || t < len) ? col[(long long)(start + t) * nx] : czero<R>();
     const cx<R> fl = (len > 0 && start >= 1) ? col[(long long)(start - 1) * nx] : czero<R>();
     const cx<R> fr = (len > 0 && start + len < ny) ? col[(long long)(start + len) * nx] : czero<R>();
-    cx<R> r[L];
 #pragma unroll
     for (int t = 0; t < L; ++t) {
-        if (t < len) {
+        if (FULL || t < len) {
             const cx<R> left = t == 0 ? fl : f[t > 0 ? t - 1 : 0];
-            const cx<R> right = (t + 1 < L && t + 1 < len) ? f[t + 1 < L ? t + 1 : 0] : fr;
+            const cx<R> right = FULL ? (t + 1 < L ? f[t + 1 < L ? t + 1 : 0] : fr)
+                                     : ((t + 1 < L && t + 1 < len) ? f[t + 1 < L ? t + 1 : 0] : fr);
             r[t] = cfma(a.roff, left + right, a.rdiag * f[t]);
         } else {
             r[t] = czero<R>();
@@ -663,6 +648,38 @@ __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
         if (lane < 64 - TX) carry = next;
     }
     bwd_fix<R, L>(r, len, cpl, carry);
+}
+
+// Workgroup: TX adjacent columns x P chunks of L rows (blockDim = TX * P);
+// lane tid holds column tid % TX, chunk tid / TX.  grid = (ceil(nx/TX), 3):
+// one workgroup per (tile, component).
+template <typename R, int L, int TX, bool GENERAL>
+__global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
+    __shared__ cx<R> scA[2][YPASS_MAX_WAVES][TX], scB[2][YPASS_MAX_WAVES][TX];
+    __shared__ double red[YPASS_MAX_WAVES];
+    const int nx = a.nx, ny = a.ny;
+    // Workgroups are dispatched round-robin over the 8 XCDs; map them so that
+    // each XCD takes a contiguous range of tiles, keeping the two tiles that
+    // share a 128-byte line in one L2.
+    const int ntx = gridDim.x;
+    const int nb = ntx * gridDim.y;
+    const int b = blockIdx.x + ntx * blockIdx.y;
+    const int tile = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int j = tile / ntx, tx = tile % ntx;
+    const int tid = threadIdx.x, c = tid % TX, k = tid / TX;
+    const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int x = tx * TX + c;
+    const bool valid = x < nx;
+    const int start = k * L;
+    const int len = valid ? max(0, min(L, ny - start)) : 0;
+    cx<R> *col = a.psi + j * a.plane + (valid ? x : 0);
+
+    // every chunk full and every column valid: loads, right-hand side and
+    // sweeps without per-element predication (uniform branch)
+    const bool full = (ny == (int)(blockDim.x / TX) * L) && (nx % TX == 0);
+    cx<R> r[L];
+    if (full) ypass_solve<R, L, TX, GENERAL, true>(a, col, start, L, k, c, lane, wave, nw, r, scA, scB);
+    else ypass_solve<R, L, TX, GENERAL, false>(a, col, start, len, k, c, lane, wave, nw, r, scA, scB);
 
     double nrm = 0.0;
 #pragma unroll
