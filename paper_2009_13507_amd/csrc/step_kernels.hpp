@@ -402,27 +402,26 @@ __device__ __forceinline__ float rol1(float x) { return __uint_as_float(dpp_rol1
 template <typename R> __device__ __forceinline__ cx<R> ror1(cx<R> v) { return {ror1(v.x), ror1(v.y)}; }
 template <typename R> __device__ __forceinline__ cx<R> rol1(cx<R> v) { return {rol1(v.x), rol1(v.y)}; }
 
-// x-pass: one workgroup of 4 wavefronts per row.  Wavefront w owns the
-// contiguous points w*RW + 64k + lane (k < K, RW = 64K, K = ceil(nx/256)),
-// so neighbours i-1, i+1 are the adjacent lanes (DPP rotations), the
-// previous / next k at the wrap-around lanes, and a two-value exchange
-// through LDS between wavefronts.  In this layout the pass applies the
-// previous RENORM, CALCNU and HERM, the SO update and the Crank-Nicolson
-// right-hand side.  The three lines are then transposed one component at a
-// time through one LDS row (so a workgroup needs only one row of LDS) into
-// the chunk layout, solved by wavefronts 0-2, and transposed back for
-// coalesced stores.
+// x-pass: one workgroup of 4 wavefronts per row.  Thread t owns the KM
+// consecutive points t*KM .. t*KM + KM - 1, so the stencil neighbours are in
+// its own registers except at its two ends: the previous thread's last and
+// the next thread's first value come by DPP whole-wave rotations, and across
+// wavefronts through a two-value LDS exchange.  In this layout the pass
+// applies the previous RENORM, CALCNU and HERM, the SO update and the
+// Crank-Nicolson right-hand side.  The three lines are then transposed one
+// component at a time through one LDS row (so a workgroup needs only one row
+// of LDS) into the chunk layout (lane l owns L points), solved by wavefronts
+// 0-2, and transposed back for the stores.
 template <typename R, int L, bool GENERAL>
 __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
-    constexpr int KM = (64 * L + XPASS_THREADS - 1) / XPASS_THREADS;  // max points per lane
+    constexpr int KM = (64 * L + XPASS_THREADS - 1) / XPASS_THREADS;  // points per thread
     extern __shared__ unsigned char smem_raw[];
     cx<R> *B = reinterpret_cast<cx<R> *>(smem_raw);  // one staged line
     const int nx = a.nx;
     cx<R> *E = B + srow<L>(nx);  // edge exchange: [2][4 waves][2 ends][3 comps]
     const int row = blockIdx.x;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int K = (nx + XPASS_THREADS - 1) / XPASS_THREADS;
-    const int RW = 64 * K;
+    const int i0 = tid * KM;  // this thread's points: i0 .. i0 + KM - 1
     const long long roff = (long long)row * nx;
     const cx<R> *src = a.src + roff;
 
@@ -430,10 +429,9 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
     cx<R> v[3][KM];
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        const int i = w * RW + 64 * k + lane;
-        const bool ok = k < K && i < nx;
+        const int i = i0 + k;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) v[j][k] = ok ? src[j * a.plane + i] : czero<R>();
+        for (int j = 0; j < 3; ++j) v[j][k] = i < nx ? src[j * a.plane + i] : czero<R>();
     }
     {
         R d0 = R(1), d1 = R(1), d2 = R(1);
@@ -446,8 +444,8 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
         const R vy = R(0.5) * a.m.kappa2 * yv * yv;
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
-            const int i = w * RW + 64 * k + lane;
-            if (k < K && i < nx) {
+            const int i = i0 + k;
+            if (i < nx) {
                 if (a.dscale) {
                     v[0][k] = d0 * v[0][k];
                     v[1][k] = d1 * v[1][k];
@@ -461,61 +459,61 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
         }
     }
 
-    // neighbour values at i-1 / i+1 of x[k] for all three components
+    // values just outside this thread's points: the previous thread's last
+    // and the next thread's first (DPP within the wavefront, LDS between)
     auto exchange_edges = [&](cx<R> (&x)[3][KM], int round) {
         cx<R> *Er = E + round * 24;
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                if (lane == 0 && k == 0) Er[(w * 2 + 0) * 3 + j] = x[j][k];
-                if (lane == 63 && k == K - 1) Er[(w * 2 + 1) * 3 + j] = x[j][k];
-            }
+        for (int j = 0; j < 3; ++j) {
+            if (lane == 0) Er[(w * 2 + 0) * 3 + j] = x[j][0];
+            if (lane == 63) Er[(w * 2 + 1) * 3 + j] = x[j][KM - 1];
         }
     };
-    auto neighbours = [&](cx<R> (&x)[3][KM], int round, int j, int k, cx<R> &prev, cx<R> &next) {
+    auto outer = [&](cx<R> (&x)[3][KM], int round, int j, cx<R> &before, cx<R> &after) {
         const cx<R> *Er = E + round * 24;
-        const cx<R> r0 = ror1(x[j][k]);
-        const cx<R> rm = ror1(x[j][k > 0 ? k - 1 : 0]);
-        const cx<R> l0 = rol1(x[j][k]);
-        const cx<R> lp = rol1(x[j][k + 1 < KM ? k + 1 : k]);
-        prev = r0;
-        next = l0;
-        if (lane == 0) prev = k > 0 ? rm : (w > 0 ? Er[((w - 1) * 2 + 1) * 3 + j] : czero<R>());
-        if (lane == 63) next = k < K - 1 ? lp : (w < 3 ? Er[((w + 1) * 2 + 0) * 3 + j] : czero<R>());
+        before = ror1(x[j][KM - 1]);
+        after = rol1(x[j][0]);
+        if (lane == 0) before = w > 0 ? Er[((w - 1) * 2 + 1) * 3 + j] : czero<R>();
+        if (lane == 63) after = w < 3 ? Er[((w + 1) * 2 + 0) * 3 + j] : czero<R>();
     };
 
     // ---- SO update u = v + q (v(i+1) - v(i-1)) [+ y-derivative terms]
     exchange_edges(v, 0);
     __syncthreads();
     cx<R> u[3][KM];
+    {
+        cx<R> vb[3], va[3];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        cx<R> pv[3], nv[3];
+        for (int jp = 0; jp < 3; ++jp) outer(v, 0, jp, vb[jp], va[jp]);
 #pragma unroll
-        for (int jp = 0; jp < 3; ++jp) neighbours(v, 0, jp, k, pv[jp], nv[jp]);
-        const int i = w * RW + 64 * k + lane;
-        const bool ok = k < K && i < nx;
+        for (int k = 0; k < KM; ++k) {
+            const int i = i0 + k;
+            const bool ok = i < nx;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            cx<R> t = v[j][k];
-#pragma unroll
-            for (int jp = 0; jp < 3; ++jp)
-                if (a.qxmask & (1u << (3 * j + jp))) t = cfma(a.qx[3 * j + jp], nv[jp] - pv[jp], t);
-            u[j][k] = ok ? t : czero<R>();
-        }
-        if (a.so_y && ok) {
-            cx<R> up[3], dn[3];
-#pragma unroll
-            for (int jp = 0; jp < 3; ++jp) {
-                up[jp] = row + 1 < a.ny ? src[jp * a.plane + nx + i] : czero<R>();
-                dn[jp] = row >= 1 ? src[jp * a.plane - nx + i] : czero<R>();
-            }
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
+            for (int j = 0; j < 3; ++j) {
+                cx<R> t = v[j][k];
 #pragma unroll
                 for (int jp = 0; jp < 3; ++jp)
-                    if (a.qymask & (1u << (3 * j + jp))) u[j][k] = cfma(a.qy[3 * j + jp], up[jp] - dn[jp], u[j][k]);
+                    if (a.qxmask & (1u << (3 * j + jp))) {
+                        const cx<R> pv = k > 0 ? v[jp][k > 0 ? k - 1 : 0] : vb[jp];
+                        const cx<R> nv = k + 1 < KM ? v[jp][k + 1 < KM ? k + 1 : 0] : va[jp];
+                        t = cfma(a.qx[3 * j + jp], nv - pv, t);
+                    }
+                u[j][k] = ok ? t : czero<R>();
+            }
+            if (a.so_y && ok) {
+                cx<R> up[3], dn[3];
+#pragma unroll
+                for (int jp = 0; jp < 3; ++jp) {
+                    up[jp] = row + 1 < a.ny ? src[jp * a.plane + nx + i] : czero<R>();
+                    dn[jp] = row >= 1 ? src[jp * a.plane - nx + i] : czero<R>();
+                }
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int jp = 0; jp < 3; ++jp)
+                        if (a.qymask & (1u << (3 * j + jp))) u[j][k] = cfma(a.qy[3 * j + jp], up[jp] - dn[jp], u[j][k]);
+            }
         }
     }
 
@@ -524,14 +522,14 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
     __syncthreads();
     cx<R> r[3][KM];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const int i = w * RW + 64 * k + lane;
-        const bool ok = k < K && i < nx;
+    for (int j = 0; j < 3; ++j) {
+        cx<R> ub, ua;
+        outer(u, 1, j, ub, ua);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            cx<R> pu, nu;
-            neighbours(u, 1, j, k, pu, nu);
-            r[j][k] = ok ? cfma(a.roff, pu + nu, a.rdiag * u[j][k]) : czero<R>();
+        for (int k = 0; k < KM; ++k) {
+            const cx<R> pu = k > 0 ? u[j][k > 0 ? k - 1 : 0] : ub;
+            const cx<R> nu = k + 1 < KM ? u[j][k + 1 < KM ? k + 1 : 0] : ua;
+            r[j][k] = i0 + k < nx ? cfma(a.roff, pu + nu, a.rdiag * u[j][k]) : czero<R>();
         }
     }
 
@@ -543,10 +541,8 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
     for (int jj = 0; jj < 3; ++jj) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int i = w * RW + 64 * k + lane;
-            if (k < K && i < nx) B[sidx<L>(i)] = r[jj][k];
-        }
+        for (int k = 0; k < KM; ++k)
+            if (i0 + k < nx) B[sidx<L>(i0 + k)] = r[jj][k];
         __syncthreads();
         if (w == jj) {
 #pragma unroll
@@ -565,10 +561,8 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int i = w * RW + 64 * k + lane;
-            if (k < K && i < nx) dst[jj * a.plane + i] = B[sidx<L>(i)];
-        }
+        for (int k = 0; k < KM; ++k)
+            if (i0 + k < nx) dst[jj * a.plane + i0 + k] = B[sidx<L>(i0 + k)];
     }
 }
 
