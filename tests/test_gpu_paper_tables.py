@@ -1,5 +1,5 @@
-"""The GPU solver against energies the paper prints (quasi-1D, DX = 0.05,
-DT = 0.00025, box [-16, 16) of 640 points; the LDS-resident 1D kernel runs
+"""The GPU solver against energies the paper prints.  Quasi-1D: DX = 0.05,
+DT = 0.00025, box [-16, 16) of 640 points (the LDS-resident 1D kernel runs
 the imaginary-time relaxation to convergence).
 
 Table 4, "spinor" column: ground-state energies at fixed magnetisation m
@@ -60,3 +60,35 @@ def test_table4_spinor_energies(name, c0, c2, m, wts, printed):
 def test_table3_so_coupled_energies(name, c0, c2, steps, printed):
     o = relax(c0, c2, (0.25, 0.5, 0.25), steps, gamma=0.5, so=api.SO_PX_SX)
     assert abs(o["E"] - printed) < 5e-5, (name, o["E"])
+
+
+# Quasi-2D, Table 4 "spinor" and SO-coupled columns (and Table 3 at DX = 0.1):
+# DX = DY = 0.1, DT = 0.0005, box [-12.8, 12.8)^2 (256^2 points), Gaussian
+# starts of width 2.  The Rashba case exercises the y-derivative SO path.
+# (The ferro SO-coupled entry is listed by the paper at m = 0.0468; from a
+# symmetric start the relaxation passes below it at m = 0, so it is not
+# used.)
+TABLE4_2D = [  # (name, c0, c2, gamma, so, m, weights, steps, printed E)
+    ("2D polar m=0", 482.0, 15.0, 0.0, api.SO_NONE, 0.0, (0.49, 0.02, 0.49), 40000, 8.3605),
+    ("2D polar m=0.3", 482.0, 15.0, 0.0, api.SO_NONE, 0.3, (0.6, 0.1, 0.3), 40000, 8.3710),
+    ("2D ferro m=0", 1327.5, -6.15, 0.0, api.SO_NONE, 0.0, (0.25, 0.5, 0.25), 40000, 13.7420),
+    ("2D polar Rashba gamma=0.5", 482.0, 15.0, 0.5, api.SO_RASHBA, 0.0, (0.25, 0.5, 0.25), 120000, 8.19690),
+]
+
+
+@pytest.mark.parametrize("name,c0,c2,gamma,so,m,wts,steps,printed", TABLE4_2D, ids=[t[0] for t in TABLE4_2D])
+def test_table4_2d_energies(name, c0, c2, gamma, so, m, wts, steps, printed):
+    n, dx = 256, 0.1
+    psi = torch.from_numpy(W.gaussian(2, n, n, dx, dx, weights=wts, width=2.0)).to("cuda:0")
+    g = api.Grid(psi, dx, dx)
+    rn = api.RENORM_FIXED_M if m != 0.0 else api.RENORM_AUTO
+    g.set_params(c0=c0, c2=c2, gamma=gamma, so=so, dt=5e-4, mag0=m, renorm=rn)
+    done = 0
+    while done < steps:
+        g.step_imag(20000)
+        done += 20000
+        o = g.observables()
+        print(f"  {done} steps: E = {o['E']:.7f}, M = {o['M']:.6f}", flush=True)
+    g.close()
+    assert abs(o["E"] - printed) < 1e-4, (name, o["E"])
+    assert abs(o["M"] - m) < 1e-10
