@@ -171,7 +171,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--obs-every", type=int, default=100)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
-    ap.add_argument("--profile-every", type=int, default=10)
+    ap.add_argument("--profile-every", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint cost ratio")

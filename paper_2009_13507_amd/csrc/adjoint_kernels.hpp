@@ -159,7 +159,7 @@ template <typename R> struct AdjXArgs {
     double *omega_partials;    // [ny] per-row Omega derivative
 };
 
-template <typename R, int L, bool GENERAL>
+template <typename R, int L, int CM>
 __global__ void __launch_bounds__(ROW_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
     extern __shared__ unsigned char smem_raw[];
     cx<R> *s = reinterpret_cast<cx<R> *>(smem_raw);
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(ROW_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
                 r[t] = czero<R>();
             }
         }
-        solve_line_wave<R, L, GENERAL>(r, start, len, a.cx_);
+        solve_line_wave<R, L, CM>(r, start, len, a.cx_);
 #pragma unroll
         for (int t = 0; t < L; ++t)
             if (t < len) sj[sidx<L>(start + t)] = r[t];

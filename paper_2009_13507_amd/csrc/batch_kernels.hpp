@@ -226,7 +226,7 @@ __device__ __forceinline__ void batch_xrow(const BatchInst<R> &I, cx<R> *psi, in
             for (int t = 0; t < L; ++t) c[t] = t < len ? B[sidx<L>(start + t)] : czero<R>();
         }
     }
-    if (w < 3) solve_line_wave<R, L, true>(c, start, len, I.lx);
+    if (w < 3) solve_line_wave<R, L, 0>(c, start, len, I.lx);
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) {
         __syncthreads();

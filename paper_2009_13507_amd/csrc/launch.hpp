@@ -43,15 +43,15 @@ template <typename R> hipError_t launch_batch_phase(hipStream_t s, const BatchAr
 hipError_t launch_batch_reset(hipStream_t s, unsigned *bar);
 
 // chunk lengths with compiled kernels (row kernels: one 64-lane wavefront
-// per line, so nx <= 64 L <= 2048)
-#define SSGP_SWITCH_L(L, GEN, CALL)                                                                   \
+// per line, so nx <= 64 L <= 2048) and coefficient modes (coef_mode)
+#define SSGP_SWITCH_L(L, CMV, CALL)                                                                   \
     switch (L) {                                                                                      \
-    case 1: return CALL(1, true);                                                                     \
-    case 2: return CALL(2, true);                                                                     \
-    case 4: return CALL(4, true);                                                                     \
-    case 8: return GEN ? CALL(8, true) : CALL(8, false);                                              \
-    case 16: return GEN ? CALL(16, true) : CALL(16, false);                                           \
-    case 32: return GEN ? CALL(32, true) : CALL(32, false);                                           \
+    case 1: return CALL(1, 0);                                                                        \
+    case 2: return CALL(2, 0);                                                                        \
+    case 4: return CMV == 4 ? CALL(4, 4) : CALL(4, 0);                                                \
+    case 8: return CMV == 4 ? CALL(8, 4) : CMV == 8 ? CALL(8, 8) : CALL(8, 0);                        \
+    case 16: return CMV == 4 ? CALL(16, 4) : CMV == 8 ? CALL(16, 8) : CALL(16, 0);                    \
+    case 32: return CMV == 4 ? CALL(32, 4) : CMV == 8 ? CALL(32, 8) : CALL(32, 0);                    \
     default: return hipErrorInvalidValue;                                                             \
     }
 

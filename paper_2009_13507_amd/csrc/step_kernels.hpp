@@ -147,15 +147,19 @@ template <typename R> struct LineCoef {
                             // chunks are below 2^-64 relative and dropped
 };
 
-// Coefficients of one chunk.  When the tabulated head fits in the first
-// chunk (head <= L, the usual case: the pivots converge within a few
-// points), c'_i is cp_inf for every chunk except the first, whose values are
-// the same for all lines and are read with wave-uniform loads; otherwise
-// (GENERAL) every lane reads its chunk's entries (clamped, unconditional
-// loads) into registers.
-template <typename R, int L, bool GENERAL> struct ChunkCoef;
+// Coefficients of one chunk.  When the tabulated head is short (head <=
+// min(L, CM), CM = 4 or 8: the pivots converge within a few points), c'_i is
+// cp_inf for every entry except the first min(L, CM) entries of the chunk
+// that starts the line: those few are selected per lane from wave-uniform
+// table loads, and every other entry is the uniform stationary value, with no
+// per-element select.  Otherwise (CM = 0) every lane reads its chunk's
+// entries (clamped, unconditional loads) into registers.
+__host__ __device__ constexpr int coef_mode(int head, int L) {
+    return L <= 2 ? 0 : head <= (L < 4 ? L : 4) ? 4 : head <= (L < 8 ? L : 8) ? 8 : 0;
+}
 
-template <typename R, int L> struct ChunkCoef<R, L, false> {
+template <typename R, int L, int CM> struct ChunkCoef {
+    static constexpr int HM = L < CM ? L : CM;  // head <= HM
     const cx<R> *tab;
     cx<R> tail;
     int head;
@@ -163,12 +167,13 @@ template <typename R, int L> struct ChunkCoef<R, L, false> {
     __device__ __forceinline__ ChunkCoef(const LineCoef<R> &C, int start)
         : tab(C.cp), tail(C.cp_inf), head(C.head), first(start == 0) {}
     __device__ __forceinline__ cx<R> operator[](int t) const {
+        if (t >= HM) return tail;  // t is a compile-time index: no select
         const cx<R> h = tab[t < head ? t : head - 1];  // uniform address
         return (first && t < head) ? h : tail;
     }
 };
 
-template <typename R, int L> struct ChunkCoef<R, L, true> {
+template <typename R, int L> struct ChunkCoef<R, L, 0> {
     cx<R> v[L];
     __device__ __forceinline__ ChunkCoef(const LineCoef<R> &C, int start) {
 #pragma unroll
@@ -268,10 +273,10 @@ __device__ __forceinline__ void wave_scan_down(cx<R> &A, cx<R> &B, int levels) {
 
 // Solves one line held by the 64 lanes of a wavefront (lane k owns
 // [start, start+len)).
-template <typename R, int L, bool GENERAL>
+template <typename R, int L, int CM>
 __device__ __forceinline__ void solve_line_wave(cx<R> (&r)[L], int start, int len, const LineCoef<R> &C) {
     const int lane = threadIdx.x & 63;
-    const ChunkCoef<R, L, GENERAL> cpl(C, start);
+    const ChunkCoef<R, L, CM> cpl(C, start);
     const cx<R> Ak = C.chunkA[lane];
     cx<R> A = Ak;
     cx<R> B = fwd_local<R, L>(r, len, cpl);
@@ -412,7 +417,7 @@ template <typename R> __device__ __forceinline__ cx<R> rol1(cx<R> v) { return {r
 // component at a time through one LDS row (so a workgroup needs only one row
 // of LDS) into the chunk layout (lane l owns L points), solved by wavefronts
 // 0-2, and transposed back for the stores.
-template <typename R, int L, bool GENERAL>
+template <typename R, int L, int CM>
 __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
     constexpr int KM = (64 * L + XPASS_THREADS - 1) / XPASS_THREADS;  // points per thread
     extern __shared__ unsigned char smem_raw[];
@@ -549,7 +554,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
             for (int t = 0; t < L; ++t) c[t] = t < len ? B[sidx<L>(start + t)] : czero<R>();
         }
     }
-    if (w < 3) solve_line_wave<R, L, GENERAL>(c, start, len, a.cx_);
+    if (w < 3) solve_line_wave<R, L, CM>(c, start, len, a.cx_);
     cx<R> *dst = a.dst + roff;
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) {
@@ -581,7 +586,7 @@ constexpr int YPASS_MAX_WAVES = YPASS_MAX_THREADS / 64;
 
 // Loads, right-hand side, elimination and chunk scans of one y-pass lane
 // (FULL: the lane holds L rows and its column is valid).
-template <typename R, int L, int TX, bool GENERAL, bool FULL>
+template <typename R, int L, int TX, int CM, bool FULL>
 __device__ __forceinline__ void ypass_solve(const YArgs<R> &a, const cx<R> *col, int start, int len, int k, int c,
                                             int lane, int wave, int nw, cx<R> (&r)[L],
                                             cx<R> (&scA)[2][YPASS_MAX_WAVES][TX],
@@ -605,7 +610,7 @@ __device__ __forceinline__ void ypass_solve(const YArgs<R> &a, const cx<R> *col,
         }
     }
 
-    const ChunkCoef<R, L, GENERAL> cpl(a.cy, start);
+    const ChunkCoef<R, L, CM> cpl(a.cy, start);
     const cx<R> Ak = a.cy.chunkA[k];
     // forward sweep and its scan over the chunks of each column
     cx<R> A = Ak;
@@ -647,7 +652,7 @@ __device__ __forceinline__ void ypass_solve(const YArgs<R> &a, const cx<R> *col,
 // Workgroup: TX adjacent columns x P chunks of L rows (blockDim = TX * P);
 // lane tid holds column tid % TX, chunk tid / TX.  grid = (ceil(nx/TX), 3):
 // one workgroup per (tile, component).
-template <typename R, int L, int TX, bool GENERAL>
+template <typename R, int L, int TX, int CM>
 __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
     __shared__ cx<R> scA[2][YPASS_MAX_WAVES][TX], scB[2][YPASS_MAX_WAVES][TX];
     __shared__ double red[YPASS_MAX_WAVES];
@@ -672,8 +677,8 @@ __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
     // sweeps without per-element predication (uniform branch)
     const bool full = (ny == (int)(blockDim.x / TX) * L) && (nx % TX == 0);
     cx<R> r[L];
-    if (full) ypass_solve<R, L, TX, GENERAL, true>(a, col, start, L, k, c, lane, wave, nw, r, scA, scB);
-    else ypass_solve<R, L, TX, GENERAL, false>(a, col, start, len, k, c, lane, wave, nw, r, scA, scB);
+    if (full) ypass_solve<R, L, TX, CM, true>(a, col, start, L, k, c, lane, wave, nw, r, scA, scB);
+    else ypass_solve<R, L, TX, CM, false>(a, col, start, len, k, c, lane, wave, nw, r, scA, scB);
 
     double nrm = 0.0;
 #pragma unroll
@@ -787,7 +792,7 @@ template <typename R> struct Args1D {
     double *renorm_out;        // last step's {d, N, fallback}, or nullptr
 };
 
-template <typename R, int L, bool GENERAL>
+template <typename R, int L, int CM>
 __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
     extern __shared__ unsigned char smem_raw[];
     cx<R> *s = reinterpret_cast<cx<R> *>(smem_raw);
@@ -821,7 +826,7 @@ __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
         cx<R> r[L];
         build_rhs_any<R, L>(j, s, nullptr, ld, nx, start, len, a.qx, a.qxmask, a.rdiag, a.roff, r);
         __syncthreads();
-        solve_line_wave<R, L, GENERAL>(r, start, len, a.cx_);
+        solve_line_wave<R, L, CM>(r, start, len, a.cx_);
         if (a.m.imag) {
             double nrm = 0.0;
 #pragma unroll
