@@ -10,8 +10,9 @@ Prints one JSON line:
   value      grid-point-steps per second over the timed steps (state resident
              in HBM when the timed region starts);
   roofline   the dominant kernel's algorithmic bytes per launch over its mean
-             duration (HIP events on the library's stream during the timed
-             region) against the 8 TB/s HBM peak;
+             duration (HIP start/stop events attached to its launches on the
+             library's stream, about every 50th step of the timed region) against
+             the 8 TB/s HBM peak;
   cpu_baseline  the CPU oracle on the host cores, on a bounded sample of the
              same workload (first steps from the same initial state).
 
@@ -22,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -171,7 +173,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--obs-every", type=int, default=100)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
-    ap.add_argument("--profile-every", type=int, default=50)
+    ap.add_argument("--profile-every", type=int, default=0,
+                    help="time the kernels of every n-th step (default: the largest n <= 50 coprime with "
+                         "--obs-every, so that every position between two observable reads is sampled alike)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint cost ratio")
@@ -207,7 +211,10 @@ def main():
 
     K = args.steps
     obs_log = []
-    g.profile(args.profile_every, capacity=K // max(1, args.profile_every) + 2)
+    every = args.profile_every
+    if every <= 0:
+        every = next(p for p in range(50, 0, -1) if math.gcd(p, args.obs_every) == 1)
+    g.profile(every, capacity=K // every + 2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     obs_log.append(g.observables())

@@ -211,9 +211,10 @@ int ssgp_batch_observables(ssgp_batch b, ssgp_obs *out);
 
 int ssgp_destroy_batch(ssgp_batch b);
 
-/* Kernel timing for measurement: with every > 0, HIP events are recorded on
- * the grid's stream around the x-pass and the y-pass of every every-th 2D
- * step, for at most capacity steps (every = 0 turns it off and frees the
+/* Kernel timing for measurement: with every > 0, the x-pass and y-pass
+ * kernels of every every-th 2D step are launched with HIP start/stop events
+ * attached (hipExtLaunchKernel), which take the kernel's own start and end
+ * times, for at most capacity steps (every = 0 turns it off and frees the
  * events).  ssgp_profile_read synchronises the stream and writes
  * out[0..4] = {profiled steps, mean x-pass ms, mean y-pass ms, min x-pass ms,
  * min y-pass ms}, then restarts the count. */

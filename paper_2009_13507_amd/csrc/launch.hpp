@@ -2,6 +2,7 @@
 // kernel family and state precision (compiled in parallel).  Each returns
 // hipSuccess or the HIP error of the launch.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "adjoint_kernels.hpp"
@@ -14,7 +15,22 @@ namespace ssgp {
 struct Launch {
     hipStream_t stream;
     int ncu;  // compute units of the device
+    // optional events that take the start and end time of the x-pass or
+    // y-pass kernel itself (hipExtLaunchKernel), for live kernel timing
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
+
+// Launches kernel<<<grid, block, lds, c.stream>>>(args), with c's timing
+// events attached when it has them.
+template <typename K, typename A>
+inline hipError_t launch_timed(const Launch &c, K kern, dim3 grid, dim3 block, size_t lds, const A &args) {
+    if (!c.ev_start) {
+        kern<<<grid, block, lds, c.stream>>>(args);
+        return hipGetLastError();
+    }
+    void *argv[] = {(void *)&args};
+    return hipExtLaunchKernel((const void *)kern, grid, block, argv, lds, c.stream, c.ev_start, c.ev_stop, 0);
+}
 
 // Dynamic LDS of the x-pass: one staged line (one padding slot per chunk)
 // and the edge exchange area of up to 8 wavefronts.

@@ -116,15 +116,17 @@ static CNHost cn_tables(int n, double h, cd s, int L, int nchunks, int max_level
 }
 
 template <typename R> struct CNDev {
-    DevBuf buf;  // cp[n] | chunkA[nchunks]
+    DevBuf buf;  // cp[n] | chunkA[nchunks] | pw[3 L]
     int n = 0, L = 0, nchunks = 0, head = 1, levels = 6;
     cx<R> rdiag{}, roff{}, cp_inf{};
     const cx<R> *cp() const { return buf.as<cx<R>>(); }
     const cx<R> *chunkA() const { return buf.as<cx<R>>() + n; }
+    const cx<R> *pw() const { return buf.as<cx<R>>() + n + nchunks; }
     LineCoef<R> coef() const {
         LineCoef<R> c;
         c.cp = cp();
         c.chunkA = chunkA();
+        c.pw = pw();
         c.cp_inf = cp_inf;
         c.head = head;
         c.levels = levels;
@@ -137,13 +139,36 @@ template <typename R> static bool same(cx<R> a, cx<R> b) { return a.x == b.x && 
 
 template <typename R>
 static int upload_cn(CNDev<R> &dst, const CNHost &h, int n, int L, int nchunks, hipStream_t st) {
-    std::vector<cx<R>> host(n + nchunks);
+    std::vector<cx<R>> host(n + nchunks + 3 * L);
     for (int i = 0; i < n; ++i) host[i] = tor<R>(h.cp[i]);
     for (int k = 0; k < nchunks; ++k) host[n + k] = tor<R>(h.chunkA[k]);
     // the pivots become stationary in the table precision: entries from
     // index head on all equal the last one
     int head = n - 1;
     while (head >= 1 && same(host[head - 1], host[n - 1])) --head;
+    // partial products of -c'_i over one chunk, from the pivots as the
+    // kernels read them (table precision, stationary beyond head): forward
+    // over a chunk of stationary pivots, backward over one, backward over
+    // the line's first chunk
+    {
+        auto piv = [&](int i) {  // entries from head on equal the last
+            const cx<R> v = host[std::min(i, n - 1)];
+            return cd((double)v.x, (double)v.y);
+        };
+        const cd tail = piv(n - 1);
+        cx<R> *pw = host.data() + n + nchunks;
+        cd f(1.0, 0.0), b(1.0, 0.0), b1(1.0, 0.0);
+        for (int t = 0; t < L; ++t) {
+            f *= -tail;
+            pw[t] = tor<R>(f);
+        }
+        for (int t = L - 1; t >= 0; --t) {
+            b *= -tail;
+            b1 *= -piv(t);
+            pw[L + t] = tor<R>(b);
+            pw[2 * L + t] = tor<R>(b1);
+        }
+    }
     SSGP_TRY(dst.buf.ensure(host.size() * sizeof(cx<R>)));
     HIP_TRY(hipMemcpyAsync(dst.buf.p, host.data(), host.size() * sizeof(cx<R>), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -264,8 +289,8 @@ struct GridCore {
     long long step_index = 0;
     DevBuf partials, renorm, obs_partials, obs_out, scratch, omega_acc, adj_partials;
     int built_mode_mask = 0;
-    // kernel timing: events around the x-pass and y-pass of every
-    // prof_every-th step (event pairs [x0, x1, y0, y1] per profiled step)
+    // kernel timing: start/stop events of the x-pass and y-pass kernels of
+    // every prof_every-th step (event pairs [x0, x1, y0, y1] per profiled step)
     int prof_every = 0, prof_cap = 0, prof_used = 0;
     long long prof_counter = 0;
     std::vector<hipEvent_t> prof_events;
@@ -347,14 +372,23 @@ template <typename R> static Model<R> model(const GridCore &g, int mode, double 
 // ------------------------------------------------------------ launches --
 static Launch lc(const GridCore &g) { return Launch{g.stream, g.ncu}; }
 
-template <typename R> static int launch_x(const GridCore &g, const XArgs<R> &a, int L) {
+template <typename R>
+static int launch_x(const GridCore &g, const XArgs<R> &a, int L, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     if (xpass_lds<R>(g.nx, L) > 160 * 1024) return fail(SSGP_EINVAL, "a row of nx=%d does not fit in LDS", g.nx);
-    LAUNCH_TRY(launch_xpass<R>(lc(g), a, L, g.dim == 2 ? g.ny : 1));
+    Launch c = lc(g);
+    c.ev_start = e0;
+    c.ev_stop = e1;
+    LAUNCH_TRY(launch_xpass<R>(c, a, L, g.dim == 2 ? g.ny : 1));
     return SSGP_OK;
 }
 
-template <typename R> static int launch_y(const GridCore &g, const YArgs<R> &a, const YShape &ys) {
-    LAUNCH_TRY(launch_ypass<R>(lc(g), a, ys.L, YTX, ys.threads));
+template <typename R>
+static int launch_y(const GridCore &g, const YArgs<R> &a, const YShape &ys, hipEvent_t e0 = nullptr,
+                    hipEvent_t e1 = nullptr) {
+    Launch c = lc(g);
+    c.ev_start = e0;
+    c.ev_stop = e1;
+    LAUNCH_TRY(launch_ypass<R>(c, a, ys.L, YTX, ys.threads));
     return SSGP_OK;
 }
 
@@ -434,7 +468,6 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
     hipEvent_t *ev = nullptr;
     if (g->prof_every > 0 && (g->prof_counter++ % g->prof_every) == 0 && g->prof_used < g->prof_cap)
         ev = &g->prof_events[(size_t)4 * g->prof_used++];
-    if (ev) HIP_TRY(hipEventRecord(ev[0], g->stream));
     const int Lx = x_chunk(g->nx);
     const YShape ys = y_shape(g->ny);
     const int ntiles = (g->nx + YTX - 1) / YTX;
@@ -459,18 +492,13 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
         XArgs<R> xa = x_args<R>(g, mode, g->scratch.p, dst, omega, nullptr);
         xa.pointwise = 0;
         xa.so_y = 1;
-        SSGP_TRY(launch_x<R>(*g, xa, Lx));
+        SSGP_TRY(launch_x<R>(*g, xa, Lx, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     } else {
         XArgs<R> xa = x_args<R>(g, mode, src, dst, omega, dscale);
-        SSGP_TRY(launch_x<R>(*g, xa, Lx));
-    }
-    if (ev) {
-        HIP_TRY(hipEventRecord(ev[1], g->stream));
-        HIP_TRY(hipEventRecord(ev[2], g->stream));
+        SSGP_TRY(launch_x<R>(*g, xa, Lx, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     }
     YArgs<R> ya = y_args<R>(g, mode, dst, imag ? g->partials.as<double>() : nullptr);
-    SSGP_TRY(launch_y<R>(*g, ya, ys));
-    if (ev) HIP_TRY(hipEventRecord(ev[3], g->stream));
+    SSGP_TRY(launch_y<R>(*g, ya, ys, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
     if (imag) {
         LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), ntiles, renorm_spec(*g),
                                           g->renorm.as<double>()));

@@ -141,6 +141,7 @@ __device__ __forceinline__ void pointwise(cx<R> &p, cx<R> &z, cx<R> &m, R V, con
 template <typename R> struct LineCoef {
     const cx<R> *cp;        // first head entries of c'_i
     const cx<R> *chunkA;    // per-chunk products of -c'_i
+    const cx<R> *pw;        // 3 L products of -c'_i over a chunk (see ChunkCoef)
     cx<R> cp_inf;
     int head;               // >= 1
     int levels;             // scan levels: carries over more than 2^levels - 1
@@ -154,6 +155,17 @@ template <typename R> struct LineCoef {
 // table loads, and every other entry is the uniform stationary value, with no
 // per-element select.  Otherwise (CM = 0) every lane reads its chunk's
 // entries (clamped, unconditional loads) into registers.
+//
+// The carry fix-ups e_t = -c'_t e_{t-1} (forward) and e_t = -c'_t e_{t+1}
+// (backward) of a chunk are products of the carry with partial products of
+// -c'_i over the chunk.  For CM != 0 these are wave-uniform, so they are
+// tabulated (pw, 3 L entries):
+//   pw[t]       = prod_{s <= t} (-cp_inf)        forward, every chunk but the
+//                                                first (whose carry is 0)
+//   pw[L + t]   = prod_{s >= t} (-cp_inf)        backward, over L - t entries
+//   pw[2 L + t] = prod_{s >= t} (-c'_s)          backward, the first chunk
+// and every fix-up entry is one independent complex multiply-add.  A chunk
+// shorter than L is the last of its line and receives a zero carry.
 __host__ __device__ constexpr int coef_mode(int head, int L) {
     return L <= 2 ? 0 : head <= (L < 4 ? L : 4) ? 4 : head <= (L < 8 ? L : 8) ? 8 : 0;
 }
@@ -161,15 +173,21 @@ __host__ __device__ constexpr int coef_mode(int head, int L) {
 template <typename R, int L, int CM> struct ChunkCoef {
     static constexpr int HM = L < CM ? L : CM;  // head <= HM
     const cx<R> *tab;
+    const cx<R> *pw;
     cx<R> tail;
     int head;
     bool first;  // this lane's chunk starts at index 0
     __device__ __forceinline__ ChunkCoef(const LineCoef<R> &C, int start)
-        : tab(C.cp), tail(C.cp_inf), head(C.head), first(start == 0) {}
+        : tab(C.cp), pw(C.pw), tail(C.cp_inf), head(C.head), first(start == 0) {}
     __device__ __forceinline__ cx<R> operator[](int t) const {
         if (t >= HM) return tail;  // t is a compile-time index: no select
         const cx<R> h = tab[t < head ? t : head - 1];  // uniform address
         return (first && t < head) ? h : tail;
+    }
+    __device__ __forceinline__ cx<R> fwd_pow(int t) const { return pw[t]; }
+    __device__ __forceinline__ cx<R> bwd_pow(int t) const {
+        if (t >= HM) return pw[L + t];
+        return first ? pw[2 * L + t] : pw[L + t];
     }
 };
 
@@ -213,6 +231,16 @@ __device__ __forceinline__ void fwd_fix(cx<R> (&r)[L], int len, const CC &cpl, c
         }
     }
 }
+template <typename R, int L, int CM>
+__device__ __forceinline__ void fwd_fix(cx<R> (&r)[L], int len, const ChunkCoef<R, L, CM> &cpl, cx<R> carry) {
+    if constexpr (CM == 0) {
+        fwd_fix<R, L, ChunkCoef<R, L, 0>>(r, len, cpl, carry);
+    } else {
+#pragma unroll
+        for (int t = 0; t < L; ++t)
+            if (t < len) r[t] = cfma(cpl.fwd_pow(t), carry, r[t]);
+    }
+}
 
 // Back substitution x_i = y_i - c'_i x_{i+1} of one chunk with zero carry-in
 // from the right.  Returns the first x (0 if empty).
@@ -234,6 +262,16 @@ __device__ __forceinline__ void bwd_fix(cx<R> (&r)[L], int len, const CC &cpl, c
             e = czero<R>() - cpl[t] * e;
             r[t] = r[t] + e;
         }
+    }
+}
+template <typename R, int L, int CM>
+__device__ __forceinline__ void bwd_fix(cx<R> (&r)[L], int len, const ChunkCoef<R, L, CM> &cpl, cx<R> carry) {
+    if constexpr (CM == 0) {
+        bwd_fix<R, L, ChunkCoef<R, L, 0>>(r, len, cpl, carry);
+    } else {
+#pragma unroll
+        for (int t = 0; t < L; ++t)
+            if (t < len) r[t] = cfma(cpl.bwd_pow(t), carry, r[t]);
     }
 }
 
@@ -416,13 +454,16 @@ template <typename R> __device__ __forceinline__ cx<R> rol1(cx<R> v) { return {r
 // Crank-Nicolson right-hand side.  The three lines are then transposed one
 // component at a time through one LDS row (so a workgroup needs only one row
 // of LDS) into the chunk layout (lane l owns L points), solved by wavefronts
-// 0-2, and transposed back for the stores.
-template <typename R, int L, int CM>
+// 0-2, and transposed back for the stores.  FULL: the row has exactly 64 L
+// points (every thread owns KM of them, every chunk is full), so no point
+// needs a range check.
+template <typename R, int L, int CM, bool FULL>
 __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
     constexpr int KM = (64 * L + XPASS_THREADS - 1) / XPASS_THREADS;  // points per thread
+    static_assert(!FULL || KM * XPASS_THREADS == 64 * L, "FULL needs 64 L = KM x threads");
     extern __shared__ unsigned char smem_raw[];
     cx<R> *B = reinterpret_cast<cx<R> *>(smem_raw);  // one staged line
-    const int nx = a.nx;
+    const int nx = FULL ? 64 * L : a.nx;
     cx<R> *E = B + srow<L>(nx);  // edge exchange: [2][4 waves][2 ends][3 comps]
     const int row = blockIdx.x;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -436,7 +477,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
     for (int k = 0; k < KM; ++k) {
         const int i = i0 + k;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) v[j][k] = i < nx ? src[j * a.plane + i] : czero<R>();
+        for (int j = 0; j < 3; ++j) v[j][k] = (FULL || i < nx) ? src[j * a.plane + i] : czero<R>();
     }
     {
         R d0 = R(1), d1 = R(1), d2 = R(1);
@@ -450,7 +491,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             const int i = i0 + k;
-            if (i < nx) {
+            if (FULL || i < nx) {
                 if (a.dscale) {
                     v[0][k] = d0 * v[0][k];
                     v[1][k] = d1 * v[1][k];
@@ -493,7 +534,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             const int i = i0 + k;
-            const bool ok = i < nx;
+            const bool ok = FULL || i < nx;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 cx<R> t = v[j][k];
@@ -534,20 +575,20 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
         for (int k = 0; k < KM; ++k) {
             const cx<R> pu = k > 0 ? u[j][k > 0 ? k - 1 : 0] : ub;
             const cx<R> nu = k + 1 < KM ? u[j][k + 1 < KM ? k + 1 : 0] : ua;
-            r[j][k] = i0 + k < nx ? cfma(a.roff, pu + nu, a.rdiag * u[j][k]) : czero<R>();
+            r[j][k] = (FULL || i0 + k < nx) ? cfma(a.roff, pu + nu, a.rdiag * u[j][k]) : czero<R>();
         }
     }
 
     // ---- transpose each component into the chunk layout, solve, transpose back
     const int start = lane * L;
-    const int len = max(0, min(L, nx - start));
+    const int len = FULL ? L : max(0, min(L, nx - start));
     cx<R> c[L];
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < KM; ++k)
-            if (i0 + k < nx) B[sidx<L>(i0 + k)] = r[jj][k];
+            if (FULL || i0 + k < nx) B[sidx<L>(i0 + k)] = r[jj][k];
         __syncthreads();
         if (w == jj) {
 #pragma unroll
@@ -567,7 +608,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < KM; ++k)
-            if (i0 + k < nx) dst[jj * a.plane + i0 + k] = B[sidx<L>(i0 + k)];
+            if (FULL || i0 + k < nx) dst[jj * a.plane + i0 + k] = B[sidx<L>(i0 + k)];
     }
 }
 
