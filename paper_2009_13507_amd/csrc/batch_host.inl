@@ -95,7 +95,7 @@ template <typename R> static int batch_build(ssgp_batch b, const long long *offs
         I.x0 = xa.x0;
         I.y0 = xa.y0;
         I.m = xa.m;
-        I.lx = xa.cx_;
+        I.lx = tables<R>(g).x[MODE_IMAG].coef();
         I.ly = T.ly[i].coef();
         I.rdx = xa.rdiag;
         I.rox = xa.roff;

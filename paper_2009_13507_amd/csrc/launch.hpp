@@ -32,15 +32,10 @@ inline hipError_t launch_timed(const Launch &c, K kern, dim3 grid, dim3 block, s
     return hipExtLaunchKernel((const void *)kern, grid, block, argv, lds, c.stream, c.ev_start, c.ev_stop, 0);
 }
 
-// Dynamic LDS of the x-pass: one staged line (one padding slot per chunk)
-// and the edge exchange area of up to 8 wavefronts.
-template <typename R> inline size_t xpass_lds(int nx, int L) {
-    return ((size_t)(nx + nx / L + 1) + 96) * sizeof(cx<R>);
-}
 // Dynamic LDS of the 1D and adjoint row kernels: all three components.
 template <typename R> inline size_t row_lds(int nx, int L) { return (size_t)3 * (nx + nx / L + 1) * sizeof(cx<R>); }
 
-template <typename R> hipError_t launch_xpass(const Launch &c, const XArgs<R> &a, int L, int rows);
+template <typename R> hipError_t launch_xpass(const Launch &c, const XArgs<R> &a, int km, int rows);
 template <typename R> hipError_t launch_ypass(const Launch &c, const YArgs<R> &a, int L, int tx, int threads);
 template <typename R> hipError_t launch_step1d(const Launch &c, const Args1D<R> &a, int L);
 template <typename R> hipError_t launch_adj_xpass(const Launch &c, const AdjXArgs<R> &a, int L, int rows);

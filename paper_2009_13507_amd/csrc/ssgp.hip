@@ -189,8 +189,11 @@ static int pow2_at_least(int v) {
     return p;
 }
 
-// chunk length of an x line handled by one 64-lane wavefront
+// chunk length of an x line handled by one 64-lane wavefront (1D and
+// adjoint row kernels, batched x rows)
 static int x_chunk(int nx) { return pow2_at_least((nx + 63) / 64); }
+// points per thread of the 2D x-pass (256 threads per row)
+static int x_block(int nx) { return pow2_at_least((nx + 255) / 256); }
 
 // y-pass shape: TX columns per workgroup, chunks of L rows, P chunks.
 // Tiles of 4 columns (64-byte row segments in FP64; the two tiles of a
@@ -300,7 +303,9 @@ struct GridCore {
 };
 
 template <typename R> struct Tables {
-    CNDev<R> x[NMODES], y[NMODES];
+    CNDev<R> x[NMODES];   // x lines as 64 chunks (1D, adjoint and batched rows)
+    CNDev<R> xb[NMODES];  // x lines as 256 chunks (2D x-pass)
+    CNDev<R> y[NMODES];
 };
 
 struct ssgp_grid_s : GridCore {
@@ -331,6 +336,9 @@ template <typename R> static int build_tables(ssgp_grid g, int mode) {
     const int Lx = x_chunk(g->nx);
     SSGP_TRY(upload_cn<R>(T.x[mode], cn_tables(g->nx, g->dx, s, Lx, 64, 6), g->nx, Lx, 64, g->stream));
     if (g->dim == 2) {
+        const int km = x_block(g->nx);
+        SSGP_TRY(upload_cn<R>(T.xb[mode], cn_tables(g->nx, g->dx, s, km, XPASS_THREADS, 6), g->nx, km, XPASS_THREADS,
+                              g->stream));
         const YShape ys = y_shape(g->ny);
         int maxlv = 0;
         while ((YTX << maxlv) < 64) ++maxlv;
@@ -373,12 +381,11 @@ template <typename R> static Model<R> model(const GridCore &g, int mode, double 
 static Launch lc(const GridCore &g) { return Launch{g.stream, g.ncu}; }
 
 template <typename R>
-static int launch_x(const GridCore &g, const XArgs<R> &a, int L, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-    if (xpass_lds<R>(g.nx, L) > 160 * 1024) return fail(SSGP_EINVAL, "a row of nx=%d does not fit in LDS", g.nx);
+static int launch_x(const GridCore &g, const XArgs<R> &a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     Launch c = lc(g);
     c.ev_start = e0;
     c.ev_stop = e1;
-    LAUNCH_TRY(launch_xpass<R>(c, a, L, g.dim == 2 ? g.ny : 1));
+    LAUNCH_TRY(launch_xpass<R>(c, a, x_block(g.nx), g.ny));
     return SSGP_OK;
 }
 
@@ -423,7 +430,7 @@ static XArgs<R> x_args(ssgp_grid g, int mode, const void *src, void *dst, double
     a.m = model<R>(*g, mode, omega);
     a.dscale = dscale;
     a.pointwise = 1;
-    a.cx_ = T.x[mode].coef();
+    a.cx_ = T.xb[mode].coef();
     a.rdiag = T.x[mode].rdiag;
     a.roff = T.x[mode].roff;
     fill_so(a, *g, mode);
@@ -468,7 +475,6 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
     hipEvent_t *ev = nullptr;
     if (g->prof_every > 0 && (g->prof_counter++ % g->prof_every) == 0 && g->prof_used < g->prof_cap)
         ev = &g->prof_events[(size_t)4 * g->prof_used++];
-    const int Lx = x_chunk(g->nx);
     const YShape ys = y_shape(g->ny);
     const int ntiles = (g->nx + YTX - 1) / YTX;
     if (so_has_y(g->p.so) && g->p.gamma != 0.0) {
@@ -492,10 +498,10 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
         XArgs<R> xa = x_args<R>(g, mode, g->scratch.p, dst, omega, nullptr);
         xa.pointwise = 0;
         xa.so_y = 1;
-        SSGP_TRY(launch_x<R>(*g, xa, Lx, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
+        SSGP_TRY(launch_x<R>(*g, xa, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     } else {
         XArgs<R> xa = x_args<R>(g, mode, src, dst, omega, dscale);
-        SSGP_TRY(launch_x<R>(*g, xa, Lx, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
+        SSGP_TRY(launch_x<R>(*g, xa, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     }
     YArgs<R> ya = y_args<R>(g, mode, dst, imag ? g->partials.as<double>() : nullptr);
     SSGP_TRY(launch_y<R>(*g, ya, ys, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));

@@ -413,7 +413,7 @@ template <typename R> struct XArgs {
     Model<R> m;
     const double *dscale;      // RENORM factors to apply first, or nullptr
     int pointwise;             // 1: CALCNU + HERM in this pass
-    LineCoef<R> cx_;           // CN_x elimination coefficients (64 chunks)
+    LineCoef<R> cx_;           // CN_x elimination coefficients (256 chunks of KM points)
     cx<R> rdiag, roff;         // right-hand side (I - sT): diagonal, off-diagonal
     cx<R> qx[9];               // SO: psi'_j += sum_j' qx[j][j'] (psi_j'(i+1) - psi_j'(i-1))
     unsigned qxmask;           // bit 3j+j' set where qx[j][j'] != 0
@@ -445,40 +445,86 @@ __device__ __forceinline__ float rol1(float x) { return __uint_as_float(dpp_rol1
 template <typename R> __device__ __forceinline__ cx<R> ror1(cx<R> v) { return {ror1(v.x), ror1(v.y)}; }
 template <typename R> __device__ __forceinline__ cx<R> rol1(cx<R> v) { return {rol1(v.x), rol1(v.y)}; }
 
+// Three affine-map scans (one per component) over the lanes of a wavefront,
+// interleaved level by level; see wave_scan_up / wave_scan_down.
+template <typename R>
+__device__ __forceinline__ void wave_scan_up3(cx<R> (&A)[3], cx<R> (&B)[3], int levels) {
+    const int lane = threadIdx.x & 63;
+    int lv = 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1, ++lv) {
+        if (lv >= levels) break;
+        cx<R> Ap[3], Bp[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Ap[j] = shfl_up(A[j], d);
+            Bp[j] = shfl_up(B[j], d);
+        }
+        if (lane >= d) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                B[j] = cfma(A[j], Bp[j], B[j]);
+                A[j] = A[j] * Ap[j];
+            }
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void wave_scan_down3(cx<R> (&A)[3], cx<R> (&B)[3], int levels) {
+    const int lane = threadIdx.x & 63;
+    int lv = 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1, ++lv) {
+        if (lv >= levels) break;
+        cx<R> Ap[3], Bp[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Ap[j] = shfl_down(A[j], d);
+            Bp[j] = shfl_down(B[j], d);
+        }
+        if (lane + d < 64) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                B[j] = cfma(A[j], Bp[j], B[j]);
+                A[j] = A[j] * Ap[j];
+            }
+        }
+    }
+}
+
 // x-pass: one workgroup of 4 wavefronts per row.  Thread t owns the KM
-// consecutive points t*KM .. t*KM + KM - 1, so the stencil neighbours are in
-// its own registers except at its two ends: the previous thread's last and
-// the next thread's first value come by DPP whole-wave rotations, and across
-// wavefronts through a two-value LDS exchange.  In this layout the pass
-// applies the previous RENORM, CALCNU and HERM, the SO update and the
-// Crank-Nicolson right-hand side.  The three lines are then transposed one
-// component at a time through one LDS row (so a workgroup needs only one row
-// of LDS) into the chunk layout (lane l owns L points), solved by wavefronts
-// 0-2, and transposed back for the stores.  FULL: the row has exactly 64 L
-// points (every thread owns KM of them, every chunk is full), so no point
-// needs a range check.
-template <typename R, int L, int CM, bool FULL>
-__global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
-    constexpr int KM = (64 * L + XPASS_THREADS - 1) / XPASS_THREADS;  // points per thread
-    static_assert(!FULL || KM * XPASS_THREADS == 64 * L, "FULL needs 64 L = KM x threads");
-    extern __shared__ unsigned char smem_raw[];
-    cx<R> *B = reinterpret_cast<cx<R> *>(smem_raw);  // one staged line
-    const int nx = FULL ? 64 * L : a.nx;
-    cx<R> *E = B + srow<L>(nx);  // edge exchange: [2][4 waves][2 ends][3 comps]
-    const int row = blockIdx.x;
+// consecutive points t*KM .. t*KM + KM - 1 of all three components from the
+// loads to the stores, so the stencil neighbours are in its own registers
+// except at its two ends: the previous thread's last and the next thread's
+// first value come by DPP whole-wave rotations, and across wavefronts
+// through a two-value LDS exchange.  In this layout the pass applies the
+// previous RENORM, CALCNU and HERM, the SO update and the Crank-Nicolson
+// right-hand side, and solves the three lines: the row is 256 chunks of KM
+// points, one per thread; each thread eliminates its chunk for the three
+// components (three independent recurrences), the chunk maps are scanned
+// within each wavefront and carried across the 4 wavefronts through LDS, and
+// each thread applies its carry fix-ups and stores its points.  FULL: the
+// row has exactly 256 KM points, so no point needs a range check.
+template <typename R> struct XShared {
+    cx<R> E[2 * 24];                   // edges: [round][4 waves][2 ends][3 comps]
+    cx<R> scA[2][4][3], scB[2][4][3];  // wavefront maps: [sweep][wave][comp]
+};
+
+// Everything after the loads, for one row whose KM points per thread are in
+// v (zero beyond nx).
+template <typename R, int KM, int CM, bool FULL>
+__device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)[3][KM], XShared<R> &sh) {
+    cx<R> *E = sh.E;
+    auto &scA = sh.scA;
+    auto &scB = sh.scB;
+    const int nx = FULL ? XPASS_THREADS * KM : a.nx;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int i0 = tid * KM;  // this thread's points: i0 .. i0 + KM - 1
     const long long roff = (long long)row * nx;
     const cx<R> *src = a.src + roff;
 
-    // ---- load, RENORM scale, CALCNU + HERM
-    cx<R> v[3][KM];
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const int i = i0 + k;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) v[j][k] = (FULL || i < nx) ? src[j * a.plane + i] : czero<R>();
-    }
+    // ---- RENORM scale, CALCNU + HERM
     {
         R d0 = R(1), d1 = R(1), d2 = R(1);
         if (a.dscale) {
@@ -579,37 +625,79 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
         }
     }
 
-    // ---- transpose each component into the chunk layout, solve, transpose back
-    const int start = lane * L;
-    const int len = FULL ? L : max(0, min(L, nx - start));
-    cx<R> c[L];
+    // ---- Crank-Nicolson solve of the three lines, chunk = this thread's points
+    const int len = FULL ? KM : max(0, min(KM, nx - i0));
+    const ChunkCoef<R, KM, CM> cpl(a.cx_, i0);
+    const cx<R> Ak = a.cx_.chunkA[tid];
+    const int levels = a.cx_.levels;
+    cx<R> A[3], B[3];
+    // forward sweep: chunk eliminations, scan, carries across wavefronts
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-        __syncthreads();
+    for (int j = 0; j < 3; ++j) {
+        A[j] = Ak;
+        B[j] = fwd_local<R, KM>(r[j], len, cpl);
+    }
+    wave_scan_up3<R>(A, B, levels);
+    if (lane == 63) {
 #pragma unroll
-        for (int k = 0; k < KM; ++k)
-            if (FULL || i0 + k < nx) B[sidx<L>(i0 + k)] = r[jj][k];
-        __syncthreads();
-        if (w == jj) {
-#pragma unroll
-            for (int t = 0; t < L; ++t) c[t] = t < len ? B[sidx<L>(start + t)] : czero<R>();
+        for (int j = 0; j < 3; ++j) {
+            scA[0][w][j] = A[j];
+            scB[0][w][j] = B[j];
         }
     }
-    if (w < 3) solve_line_wave<R, L, CM>(c, start, len, a.cx_);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        cx<R> carry = czero<R>();
+        for (int q = 0; q < w; ++q) carry = cfma(scA[0][q][j], carry, scB[0][q][j]);
+        const cx<R> prev = shfl_up(cfma(A[j], carry, B[j]), 1);
+        if (lane >= 1) carry = prev;
+        fwd_fix<R, KM>(r[j], len, cpl, carry);
+    }
+    // back substitution: chunk sweeps, reverse scan, carries
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        A[j] = Ak;
+        B[j] = bwd_local<R, KM>(r[j], len, cpl);
+    }
+    wave_scan_down3<R>(A, B, levels);
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            scA[1][w][j] = A[j];
+            scB[1][w][j] = B[j];
+        }
+    }
+    __syncthreads();
     cx<R> *dst = a.dst + roff;
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-        __syncthreads();
-        if (w == jj) {
-#pragma unroll
-            for (int t = 0; t < L; ++t)
-                if (t < len) B[sidx<L>(start + t)] = c[t];
-        }
-        __syncthreads();
+    for (int j = 0; j < 3; ++j) {
+        cx<R> carry = czero<R>();
+        for (int q = 3; q > w; --q) carry = cfma(scA[1][q][j], carry, scB[1][q][j]);
+        const cx<R> next = shfl_down(cfma(A[j], carry, B[j]), 1);
+        if (lane < 63) carry = next;
+        bwd_fix<R, KM>(r[j], len, cpl, carry);
 #pragma unroll
         for (int k = 0; k < KM; ++k)
-            if (FULL || i0 + k < nx) dst[jj * a.plane + i0 + k] = B[sidx<L>(i0 + k)];
+            if (FULL || i0 + k < nx) dst[j * a.plane + i0 + k] = r[j][k];
     }
+}
+
+template <typename R, int KM, int CM, bool FULL>
+__global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
+    __shared__ XShared<R> sh;
+    const int nx = FULL ? XPASS_THREADS * KM : a.nx;
+    const int row = blockIdx.x;
+    const int i0 = threadIdx.x * KM;
+    const cx<R> *src = a.src + (long long)row * nx;
+    cx<R> v[3][KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const int i = i0 + k;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v[j][k] = (FULL || i < nx) ? src[j * a.plane + i] : czero<R>();
+    }
+    xpass_row<R, KM, CM, FULL>(a, row, v, sh);
 }
 
 // ------------------------------------------------------------- y-pass ---
