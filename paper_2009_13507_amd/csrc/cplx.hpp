@@ -70,9 +70,9 @@ template <typename R> __host__ __device__ __forceinline__ R cosh_q(R q) { return
 
 // Largest u^2 for which the series above are used.
 template <typename R> struct SeriesLimit { static constexpr R q = R(0.6168502750680849); };  // (pi/4)^2
-// Shorter series: with q <= 1e-2 the first omitted term of a 6-term series
-// is below 2e-22 relative, with q <= 1e-4 that of a 4-term series is below
-// 3e-22.  A wavefront takes the shortest series valid for all its lanes.
-constexpr double SERIES_Q6 = 1e-2, SERIES_Q4 = 1e-4;
+// Shorter series: with q <= SERIES_Qn the first omitted term of the n-term
+// series, q^n / (2n)!, is below 2^-60 relative (the sums are >= 0.99 there).
+// A wavefront takes the shortest series valid for all its lanes.
+constexpr double SERIES_Q2 = 4e-9, SERIES_Q3 = 8e-6, SERIES_Q4 = 4e-4, SERIES_Q5 = 4.5e-3, SERIES_Q6 = 2.5e-2;
 
 } // namespace ssgp

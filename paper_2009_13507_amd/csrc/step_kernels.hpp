@@ -48,11 +48,18 @@ __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
 
 // cos(th), sin(th); Taylor series for |th| <= pi/4 (as short as every lane
 // of the wavefront allows), library call beyond.
+template <typename R, int N> __device__ __forceinline__ void cos_sin_n(R th, R q, R &c, R &s) {
+    s = th * series_q<R, true, 1, N>(q);
+    c = series_q<R, true, 0, N>(q);
+}
 template <typename R> __device__ __forceinline__ void cos_sin(R th, R &c, R &s) {
     const R q = th * th;
-    if (__all(q <= R(SERIES_Q6))) {
-        s = th * series_q<R, true, 1, 6>(q);
-        c = series_q<R, true, 0, 6>(q);
+    if (__all(q <= R(SERIES_Q4))) {
+        cos_sin_n<R, 4>(th, q, c, s);
+    } else if (__all(q <= R(SERIES_Q5))) {
+        cos_sin_n<R, 5>(th, q, c, s);
+    } else if (__all(q <= R(SERIES_Q6))) {
+        cos_sin_n<R, 6>(th, q, c, s);
     } else if (q <= SeriesLimit<R>::q) {
         s = th * sinc_q(q);
         c = cos_q(q);
@@ -72,40 +79,41 @@ template <typename R> __device__ __forceinline__ void cos_sin(R th, R &c, R &s) 
 //          (cos(C dt) - 1)/C^2 = -(dt^2/2) sinc(u)^2 (hyperbolic analogues in
 //          imaginary time), all series in u^2 = dt^2 C^2 / 4: no square
 //          root, no division, and no special case at C = 0.
+
+// The three CALCNU exponents dt phi_j at one point.
 template <typename R>
-__device__ __forceinline__ void pointwise(cx<R> &p, cx<R> &z, cx<R> &m, R V, const Model<R> &M) {
+__device__ __forceinline__ void calcnu_phases(const cx<R> &p, const cx<R> &z, const cx<R> &m, R V,
+                                              const Model<R> &M, R (&th)[3]) {
     const R rp = abs2(p), r0 = abs2(z), rm = abs2(m);
-    const R rho = rp + r0 + rm;
-    const R base = V + M.c0 * rho;
-    const R php = base + M.c2 * (rp - rm + r0);
-    const R ph0 = base + M.c2 * (rp + rm);
-    const R phm = base + M.c2 * (rm - rp + r0);
-    if (M.imag) {
-        p = exp_(-M.dt * php) * p;
-        z = exp_(-M.dt * ph0) * z;
-        m = exp_(-M.dt * phm) * m;
-    } else {
-        R c, s;
-        cos_sin(M.dt * php, c, s);
-        p = p * mk(c, -s);
-        cos_sin(M.dt * ph0, c, s);
-        z = z * mk(c, -s);
-        cos_sin(M.dt * phm, c, s);
-        m = m * mk(c, -s);
-    }
-    const cx<R> a = cfma(mk(M.c2, R(0)), conj(m) * z, mk(M.om_t, R(0)));
-    const cx<R> b = cfma(mk(M.c2, R(0)), conj(z) * p, mk(M.om_t, R(0)));
-    const R q = R(0.25) * M.dt * M.dt * (abs2(a) + abs2(b));
-    R S, C;
-    if (__all(q <= R(SERIES_Q4))) {
-        S = M.imag ? series_q<R, false, 1, 4>(q) : series_q<R, true, 1, 4>(q);
-        C = M.imag ? series_q<R, false, 0, 4>(q) : series_q<R, true, 0, 4>(q);
+    const R base = V + M.c0 * (rp + r0 + rm);
+    th[0] = M.dt * (base + M.c2 * (rp - rm + r0));
+    th[1] = M.dt * (base + M.c2 * (rp + rm));
+    th[2] = M.dt * (base + M.c2 * (rm - rp + r0));
+}
+
+// HERM off-diagonals a, b and u^2 = dt^2 (|a|^2 + |b|^2) / 4 at one point.
+template <typename R>
+__device__ __forceinline__ R herm_ab(const cx<R> &p, const cx<R> &z, const cx<R> &m, const Model<R> &M, cx<R> &a,
+                                     cx<R> &b) {
+    a = cfma(mk(M.c2, R(0)), conj(m) * z, mk(M.om_t, R(0)));
+    b = cfma(mk(M.c2, R(0)), conj(z) * p, mk(M.om_t, R(0)));
+    return R(0.25) * M.dt * M.dt * (abs2(a) + abs2(b));
+}
+
+// S = sinc(u) (sinhc in imaginary time) and C = cos(u) (cosh) from q = u^2:
+// NT-term series, or (NT = 0) the 10-term series up to (pi/4)^2 and the
+// library beyond.
+template <typename R, int NT>
+__device__ __forceinline__ void herm_sc(R q, int imag, R &S, R &C) {
+    if (NT > 0) {
+        S = imag ? series_q<R, false, 1, NT>(q) : series_q<R, true, 1, NT>(q);
+        C = imag ? series_q<R, false, 0, NT>(q) : series_q<R, true, 0, NT>(q);
     } else if (q <= SeriesLimit<R>::q) {
-        S = M.imag ? sinhc_q(q) : sinc_q(q);
-        C = M.imag ? cosh_q(q) : cos_q(q);
+        S = imag ? sinhc_q(q) : sinc_q(q);
+        C = imag ? cosh_q(q) : cos_q(q);
     } else {
         const R u = sqrt_(q);
-        if (M.imag) {
+        if (imag) {
             S = sinh_(u) / u;
             C = cosh_(u);
         } else {
@@ -115,6 +123,11 @@ __device__ __forceinline__ void pointwise(cx<R> &p, cx<R> &z, cx<R> &m, R V, con
             C = cu;
         }
     }
+}
+
+template <typename R>
+__device__ __forceinline__ void herm_apply(cx<R> &p, cx<R> &z, cx<R> &m, cx<R> a, cx<R> b, R S, R C,
+                                           const Model<R> &M) {
     const cx<R> A0 = a * z, A1 = cfma(conj(a), p, b * m), A2 = conj(b) * z;
     const cx<R> B0 = a * A1, B1 = cfma(conj(a), A0, b * A2), B2 = conj(b) * A1;
     const R f = -M.dt * S * C;
@@ -128,6 +141,32 @@ __device__ __forceinline__ void pointwise(cx<R> &p, cx<R> &z, cx<R> &m, R V, con
         z = z + f * mul_i(A1) + h * B1;
         m = m + f * mul_i(A2) + h * B2;
     }
+}
+
+template <typename R>
+__device__ __forceinline__ void pointwise(cx<R> &p, cx<R> &z, cx<R> &m, R V, const Model<R> &M) {
+    R th[3];
+    calcnu_phases(p, z, m, V, M, th);
+    if (M.imag) {
+        p = exp_(-th[0]) * p;
+        z = exp_(-th[1]) * z;
+        m = exp_(-th[2]) * m;
+    } else {
+        R c, s;
+        cos_sin(th[0], c, s);
+        p = p * mk(c, -s);
+        cos_sin(th[1], c, s);
+        z = z * mk(c, -s);
+        cos_sin(th[2], c, s);
+        m = m * mk(c, -s);
+    }
+    cx<R> a, b;
+    const R q = herm_ab(p, z, m, M, a, b);
+    R S, C;
+    if (__all(q <= R(SERIES_Q2))) herm_sc<R, 2>(q, M.imag, S, C);
+    else if (__all(q <= R(SERIES_Q4))) herm_sc<R, 4>(q, M.imag, S, C);
+    else herm_sc<R, 0>(q, M.imag, S, C);
+    herm_apply(p, z, m, a, b, S, C, M);
 }
 
 // -------------------------------------------------- chunked line solve ---
@@ -272,6 +311,41 @@ __device__ __forceinline__ void bwd_fix(cx<R> (&r)[L], int len, const ChunkCoef<
 #pragma unroll
         for (int t = 0; t < L; ++t)
             if (t < len) r[t] = cfma(cpl.bwd_pow(t), carry, r[t]);
+    }
+}
+
+// The fix-ups of three lines with the same chunk coefficients, entry by
+// entry (each tabulated product is loaded once for the three lines).
+template <typename R, int L, int CM>
+__device__ __forceinline__ void fwd_fix3(cx<R> (&r)[3][L], int len, const ChunkCoef<R, L, CM> &cpl,
+                                         const cx<R> (&carry)[3]) {
+    if constexpr (CM == 0) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) fwd_fix<R, L>(r[j], len, cpl, carry[j]);
+    } else {
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            const cx<R> P = cpl.fwd_pow(t);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                if (t < len) r[j][t] = cfma(P, carry[j], r[j][t]);
+        }
+    }
+}
+template <typename R, int L, int CM>
+__device__ __forceinline__ void bwd_fix3(cx<R> (&r)[3][L], int len, const ChunkCoef<R, L, CM> &cpl,
+                                         const cx<R> (&carry)[3]) {
+    if constexpr (CM == 0) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) bwd_fix<R, L>(r[j], len, cpl, carry[j]);
+    } else {
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            const cx<R> P = cpl.bwd_pow(t);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                if (t < len) r[j][t] = cfma(P, carry[j], r[j][t]);
+        }
     }
 }
 
@@ -505,7 +579,8 @@ __device__ __forceinline__ void wave_scan_down3(cx<R> (&A)[3], cx<R> (&B)[3], in
 // components (three independent recurrences), the chunk maps are scanned
 // within each wavefront and carried across the 4 wavefronts through LDS, and
 // each thread applies its carry fix-ups and stores its points.  FULL: the
-// row has exactly 256 KM points, so no point needs a range check.
+// row has exactly 256 KM points, so no point needs a range check.  SOY: the
+// SO form has y derivatives (terms with rows iy +- 1 of src).
 template <typename R> struct XShared {
     cx<R> E[2 * 24];                   // edges: [round][4 waves][2 ends][3 comps]
     cx<R> scA[2][4][3], scB[2][4][3];  // wavefront maps: [sweep][wave][comp]
@@ -513,7 +588,7 @@ template <typename R> struct XShared {
 
 // Everything after the loads, for one row whose KM points per thread are in
 // v (zero beyond nx).
-template <typename R, int KM, int CM, bool FULL>
+template <typename R, int KM, int CM, bool FULL, bool SOY>
 __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)[3][KM], XShared<R> &sh) {
     cx<R> *E = sh.E;
     auto &scA = sh.scA;
@@ -578,22 +653,33 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
 #pragma unroll
         for (int jp = 0; jp < 3; ++jp) outer(v, 0, jp, vb[jp], va[jp]);
 #pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < KM; ++k) u[j][k] = v[j][k];
+        // one coefficient at a time over the thread's points (the terms of
+        // each point are still added in the order jp = 0, 1, 2)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int jp = 0; jp < 3; ++jp)
+                if (a.qxmask & (1u << (3 * j + jp))) {
+                    const cx<R> q = a.qx[3 * j + jp];
+#pragma unroll
+                    for (int k = 0; k < KM; ++k) {
+                        const cx<R> pv = k > 0 ? v[jp][k > 0 ? k - 1 : 0] : vb[jp];
+                        const cx<R> nv = k + 1 < KM ? v[jp][k + 1 < KM ? k + 1 : 0] : va[jp];
+                        u[j][k] = cfma(q, nv - pv, u[j][k]);
+                    }
+                }
+#pragma unroll
         for (int k = 0; k < KM; ++k) {
             const int i = i0 + k;
             const bool ok = FULL || i < nx;
+            if (!ok) {
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                cx<R> t = v[j][k];
-#pragma unroll
-                for (int jp = 0; jp < 3; ++jp)
-                    if (a.qxmask & (1u << (3 * j + jp))) {
-                        const cx<R> pv = k > 0 ? v[jp][k > 0 ? k - 1 : 0] : vb[jp];
-                        const cx<R> nv = k + 1 < KM ? v[jp][k + 1 < KM ? k + 1 : 0] : va[jp];
-                        t = cfma(a.qx[3 * j + jp], nv - pv, t);
-                    }
-                u[j][k] = ok ? t : czero<R>();
+                for (int j = 0; j < 3; ++j) u[j][k] = czero<R>();
             }
-            if (a.so_y && ok) {
+            if (SOY && ok) {
                 cx<R> up[3], dn[3];
 #pragma unroll
                 for (int jp = 0; jp < 3; ++jp) {
@@ -646,14 +732,15 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         }
     }
     __syncthreads();
+    cx<R> carry[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        cx<R> carry = czero<R>();
-        for (int q = 0; q < w; ++q) carry = cfma(scA[0][q][j], carry, scB[0][q][j]);
-        const cx<R> prev = shfl_up(cfma(A[j], carry, B[j]), 1);
-        if (lane >= 1) carry = prev;
-        fwd_fix<R, KM>(r[j], len, cpl, carry);
+        carry[j] = czero<R>();
+        for (int q = 0; q < w; ++q) carry[j] = cfma(scA[0][q][j], carry[j], scB[0][q][j]);
+        const cx<R> prev = shfl_up(cfma(A[j], carry[j], B[j]), 1);
+        if (lane >= 1) carry[j] = prev;
     }
+    fwd_fix3<R, KM>(r, len, cpl, carry);
     // back substitution: chunk sweeps, reverse scan, carries
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -672,18 +759,20 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     cx<R> *dst = a.dst + roff;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        cx<R> carry = czero<R>();
-        for (int q = 3; q > w; --q) carry = cfma(scA[1][q][j], carry, scB[1][q][j]);
-        const cx<R> next = shfl_down(cfma(A[j], carry, B[j]), 1);
-        if (lane < 63) carry = next;
-        bwd_fix<R, KM>(r[j], len, cpl, carry);
+        carry[j] = czero<R>();
+        for (int q = 3; q > w; --q) carry[j] = cfma(scA[1][q][j], carry[j], scB[1][q][j]);
+        const cx<R> next = shfl_down(cfma(A[j], carry[j], B[j]), 1);
+        if (lane < 63) carry[j] = next;
+    }
+    bwd_fix3<R, KM>(r, len, cpl, carry);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int k = 0; k < KM; ++k)
             if (FULL || i0 + k < nx) dst[j * a.plane + i0 + k] = r[j][k];
-    }
 }
 
-template <typename R, int KM, int CM, bool FULL>
+template <typename R, int KM, int CM, bool FULL, bool SOY>
 __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
     __shared__ XShared<R> sh;
     const int nx = FULL ? XPASS_THREADS * KM : a.nx;
@@ -697,7 +786,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) v[j][k] = (FULL || i < nx) ? src[j * a.plane + i] : czero<R>();
     }
-    xpass_row<R, KM, CM, FULL>(a, row, v, sh);
+    xpass_row<R, KM, CM, FULL, SOY>(a, row, v, sh);
 }
 
 // ------------------------------------------------------------- y-pass ---
