@@ -732,11 +732,21 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         }
     }
     __syncthreads();
-    cx<R> carry[3];
+    // carry into this wavefront: the maps of the wavefronts before it, in
+    // order, the three components' entries of one wavefront read together
+    cx<R> carry[3] = {czero<R>(), czero<R>(), czero<R>()};
+    for (int q = 0; q < w; ++q) {
+        cx<R> mA[3], mB[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            mA[j] = scA[0][q][j];
+            mB[j] = scB[0][q][j];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) carry[j] = cfma(mA[j], carry[j], mB[j]);
+    }
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        carry[j] = czero<R>();
-        for (int q = 0; q < w; ++q) carry[j] = cfma(scA[0][q][j], carry[j], scB[0][q][j]);
         const cx<R> prev = shfl_up(cfma(A[j], carry[j], B[j]), 1);
         if (lane >= 1) carry[j] = prev;
     }
@@ -758,9 +768,19 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     __syncthreads();
     cx<R> *dst = a.dst + roff;
 #pragma unroll
+    for (int j = 0; j < 3; ++j) carry[j] = czero<R>();
+    for (int q = 3; q > w; --q) {
+        cx<R> mA[3], mB[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            mA[j] = scA[1][q][j];
+            mB[j] = scB[1][q][j];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) carry[j] = cfma(mA[j], carry[j], mB[j]);
+    }
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
-        carry[j] = czero<R>();
-        for (int q = 3; q > w; --q) carry[j] = cfma(scA[1][q][j], carry[j], scB[1][q][j]);
         const cx<R> next = shfl_down(cfma(A[j], carry[j], B[j]), 1);
         if (lane < 63) carry[j] = next;
     }
@@ -773,7 +793,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
 }
 
 template <typename R, int KM, int CM, bool FULL, bool SOY>
-__global__ void __launch_bounds__(XPASS_THREADS) xpass_kernel(XArgs<R> a) {
+__global__ void __launch_bounds__(XPASS_THREADS) __attribute__((amdgpu_waves_per_eu(KM <= 4 ? 4 : 1))) xpass_kernel(XArgs<R> a) {
     __shared__ XShared<R> sh;
     const int nx = FULL ? XPASS_THREADS * KM : a.nx;
     const int row = blockIdx.x;
