@@ -581,15 +581,86 @@ __device__ __forceinline__ void wave_scan_down3(cx<R> (&A)[3], cx<R> (&B)[3], in
 // each thread applies its carry fix-ups and stores its points.  FULL: the
 // row has exactly 256 KM points, so no point needs a range check.  SOY: the
 // SO form has y derivatives (terms with rows iy +- 1 of src).
-template <typename R> struct XShared {
+template <typename R, int KM> struct XShared {
     cx<R> E[2 * 24];                   // edges: [round][4 waves][2 ends][3 comps]
     cx<R> scA[2][4][3], scB[2][4][3];  // wavefront maps: [sweep][wave][comp]
+    cx<R> xch[4][KM > 1 ? 64 * KM + 64 : 1];  // per-wavefront store line (see store_row)
 };
+
+// Stores of one row.  Wavefront w holds the 64 KM consecutive points
+// 64 KM w + p, p < 64 KM, of the row in the blocked order (lane l: points
+// p = KM l + m).  The stores are coalesced (store k of lane l: point
+// p = 64 k + l): the blocked values pass through the wavefront's own LDS
+// line, one padding slot after every KM points so that the blocked accesses
+// (stride KM + 1 slots) spread over the banks.  A wavefront's LDS operations
+// complete in issue order, so a wavefront-level compiler barrier orders
+// them.  All three components are read back before the first store is
+// issued (a store's data registers must not be reused while it is in
+// flight).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Complex values moved as two-element vectors (first-class values, so that
+// the copies stay in registers).
+template <typename R> using vec2 = R __attribute__((ext_vector_type(2)));
+template <typename R> __device__ __forceinline__ void put2(cx<R> *p, cx<R> v) {
+    *reinterpret_cast<vec2<R> *>(p) = vec2<R>{v.x, v.y};
+}
+template <typename R> __device__ __forceinline__ cx<R> get2(const cx<R> *p) {
+    const vec2<R> t = *reinterpret_cast<const vec2<R> *>(p);
+    return cx<R>{t.x, t.y};
+}
+
+// blocked b[m] (point KM lane + m) -> coalesced c[k] (point 64 k + lane)
+template <typename R, int KM>
+__device__ __forceinline__ void wave_exchange(cx<R> *line, int lane, const cx<R> (&b)[KM], cx<R> (&c)[KM]) {
+#pragma unroll
+    for (int m = 0; m < KM; ++m) {
+        const int p = KM * lane + m;
+        put2(line + p + p / KM, b[m]);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const int p = 64 * k + lane;
+        c[k] = get2(line + p + p / KM);
+    }
+    wave_lds_sync();
+}
+
+template <typename R, int KM, bool FULL>
+__device__ __forceinline__ void store_row(cx<R> *dst, long long plane, int nx, const cx<R> (&r)[3][KM],
+                                          cx<R> *line) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wbase = 64 * KM * w;
+    if constexpr (KM == 1) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (FULL || wbase + lane < nx) dst[j * plane + wbase + lane] = r[j][0];
+    } else {
+        cx<R> c0[KM], c1[KM], c2[KM];
+        wave_exchange<R, KM>(line, lane, r[0], c0);
+        wave_exchange<R, KM>(line, lane, r[1], c1);
+        wave_exchange<R, KM>(line, lane, r[2], c2);
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = wbase + 64 * k + lane;
+            if (FULL || i < nx) {
+                put2(dst + i, c0[k]);
+                put2(dst + plane + i, c1[k]);
+                put2(dst + 2 * plane + i, c2[k]);
+            }
+        }
+    }
+}
 
 // Everything after the loads, for one row whose KM points per thread are in
 // v (zero beyond nx).
 template <typename R, int KM, int CM, bool FULL, bool SOY>
-__device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)[3][KM], XShared<R> &sh) {
+__device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)[3][KM], XShared<R, KM> &sh) {
     cx<R> *E = sh.E;
     auto &scA = sh.scA;
     auto &scB = sh.scB;
@@ -785,16 +856,12 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         if (lane < 63) carry[j] = next;
     }
     bwd_fix3<R, KM>(r, len, cpl, carry);
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int k = 0; k < KM; ++k)
-            if (FULL || i0 + k < nx) dst[j * a.plane + i0 + k] = r[j][k];
+    store_row<R, KM, FULL>(dst, a.plane, nx, r, sh.xch[w]);
 }
 
 template <typename R, int KM, int CM, bool FULL, bool SOY>
 __global__ void __launch_bounds__(XPASS_THREADS) __attribute__((amdgpu_waves_per_eu(KM <= 4 ? 4 : 1))) xpass_kernel(XArgs<R> a) {
-    __shared__ XShared<R> sh;
+    __shared__ XShared<R, KM> sh;
     const int nx = FULL ? XPASS_THREADS * KM : a.nx;
     const int row = blockIdx.x;
     const int i0 = threadIdx.x * KM;
