@@ -37,7 +37,6 @@ static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps)
         a.m = model<R>(*g, MODE_REAL, omega);
         a.cx_ = T.x[MODE_ADJ].coef();
         a.rdiag = T.x[MODE_ADJ].rdiag;
-        a.roff = T.x[MODE_ADJ].roff;
         XArgs<R> tmp{};
         fill_so(tmp, *g, MODE_ADJ);
         for (int q = 0; q < 9; ++q) a.qx[q] = tmp.qx[q];

@@ -153,7 +153,7 @@ template <typename R> struct AdjXArgs {
     R dx, dy, x0, y0;
     Model<R> m;
     LineCoef<R> cx_;           // CN_x coefficients with the conjugate factor
-    cx<R> rdiag, roff;
+    cx<R> rdiag;               // diagonal of (I - sT)/o (off-diagonal -1)
     cx<R> qx[9];               // SO^H stencil couplings
     unsigned qxmask;
     double *omega_partials;    // [ny] per-row Omega derivative
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(ROW_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
         for (int t = 0; t < L; ++t) {
             if (t < len) {
                 const cx<R> un = at(start + t + 1);
-                r[t] = cfma(a.roff, um + un, a.rdiag * uc);
+                r[t] = cn_rhs(a.rdiag, uc, um + un);
                 um = uc;
                 uc = un;
             } else {

@@ -98,9 +98,7 @@ template <typename R> static int batch_build(ssgp_batch b, const long long *offs
         I.lx = tables<R>(g).x[MODE_IMAG].coef();
         I.ly = T.ly[i].coef();
         I.rdx = xa.rdiag;
-        I.rox = xa.roff;
         I.rdy = T.ly[i].rdiag;
-        I.roy = T.ly[i].roff;
         for (int q = 0; q < 9; ++q) I.qx[q] = xa.qx[q];
         I.qxmask = xa.qxmask;
         I.sp = renorm_spec(*g);

@@ -47,7 +47,7 @@ template <typename R> struct BatchInst {
     R dx, dy, x0, y0;
     Model<R> m;
     LineCoef<R> lx, ly;        // elimination coefficients of the x and y lines
-    cx<R> rdx, rox, rdy, roy;  // (I - sT)/o of x and y: diagonal, off-diagonal
+    cx<R> rdx, rdy;            // diagonal of (I - sT)/o of x and y (off-diagonal -1)
     cx<R> qx[9];               // SO: psi'_j += sum_j' qx[j][j'] (psi_j'(i+1) - psi_j'(i-1))
     unsigned qxmask;
     RenormSpec sp;
@@ -205,7 +205,7 @@ __device__ __forceinline__ void batch_xrow(const BatchInst<R> &I, cx<R> *psi, in
         for (int j = 0; j < 3; ++j) {
             cx<R> pu, nu;
             neighbours(u, 1, j, k, pu, nu);
-            r[j][k] = ok ? cfma(I.rox, pu + nu, I.rdx * u[j][k]) : czero<R>();
+            r[j][k] = ok ? cn_rhs(I.rdx, u[j][k], pu + nu) : czero<R>();
         }
     }
     // transpose into the chunk layout, solve (waves 0-2), transpose back
@@ -287,7 +287,7 @@ __device__ __forceinline__ double batch_ytile(const BatchInst<R> &I, cx<R> *psi,
         if (t < len) {
             const cx<R> left = t == 0 ? fl : f[t > 0 ? t - 1 : 0];
             const cx<R> right = (t + 1 < L && t + 1 < len) ? f[t + 1 < L ? t + 1 : 0] : fr;
-            r[t] = cfma(I.roy, left + right, I.rdy * f[t]);
+            r[t] = cn_rhs(I.rdy, f[t], left + right);
         } else {
             r[t] = czero<R>();
         }

@@ -28,6 +28,13 @@ template <typename R> __host__ __device__ __forceinline__ cx<R> cfma(cx<R> a, cx
 }
 // i * a
 template <typename R> __host__ __device__ __forceinline__ cx<R> mul_i(cx<R> a) { return {-a.y, a.x}; }
+// Crank-Nicolson right-hand side (I - sT) u / o at one point from the
+// diagonal coefficient d = (1 - s/h^2) / o, the point's value u and the sum
+// of its two neighbours: the off-diagonal s/(2h^2) / o is exactly -1, so
+// the value is d u - (u_{i-1} + u_{i+1}).
+template <typename R> __host__ __device__ __forceinline__ cx<R> cn_rhs(cx<R> d, cx<R> u, cx<R> nsum) {
+    return {fma_(d.x, u.x, fma_(-d.y, u.y, -nsum.x)), fma_(d.x, u.y, fma_(d.y, u.x, -nsum.y))};
+}
 template <typename R> __host__ __device__ __forceinline__ cx<R> czero() { return {R(0), R(0)}; }
 
 // Lane shuffles of a complex value across the 64-lane wavefront.

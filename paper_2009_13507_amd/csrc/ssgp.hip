@@ -85,7 +85,7 @@ struct DevBuf {
 // products A_k = prod_{i in chunk k} (-c'_i) (1 for empty chunks).
 struct CNHost {
     std::vector<cd> cp, chunkA;
-    cd rdiag, roff;  // (I - sT) / o: diagonal and off-diagonal
+    cd rdiag;  // (I - sT) / o: diagonal (the off-diagonal is exactly -1)
     int levels;      // scan levels needed for carries above 2^-64
 };
 
@@ -102,7 +102,6 @@ static CNHost cn_tables(int n, double h, cd s, int L, int nchunks, int max_level
         if (k * L < n) amax = std::max(amax, std::abs(t.chunkA[k]));
     }
     t.rdiag = (1.0 - s / (h * h)) / o;
-    t.roff = (s / (2.0 * h * h)) / o;
     // A carry from W+1 or more chunks back is scaled by at most amax^(W+1);
     // take the smallest W = 2^levels - 1 with amax^(W+1) <= 2^-64.
     int levels = max_levels;
@@ -118,7 +117,7 @@ static CNHost cn_tables(int n, double h, cd s, int L, int nchunks, int max_level
 template <typename R> struct CNDev {
     DevBuf buf;  // cp[n] | chunkA[nchunks] | pw[3 L]
     int n = 0, L = 0, nchunks = 0, head = 1, levels = 6;
-    cx<R> rdiag{}, roff{}, cp_inf{};
+    cx<R> rdiag{}, cp_inf{};
     const cx<R> *cp() const { return buf.as<cx<R>>(); }
     const cx<R> *chunkA() const { return buf.as<cx<R>>() + n; }
     const cx<R> *pw() const { return buf.as<cx<R>>() + n + nchunks; }
@@ -179,7 +178,6 @@ static int upload_cn(CNDev<R> &dst, const CNHost &h, int n, int L, int nchunks, 
     dst.levels = h.levels;
     dst.cp_inf = host[n - 1];
     dst.rdiag = tor<R>(h.rdiag);
-    dst.roff = tor<R>(h.roff);
     return SSGP_OK;
 }
 
@@ -432,7 +430,6 @@ static XArgs<R> x_args(ssgp_grid g, int mode, const void *src, void *dst, double
     a.pointwise = 1;
     a.cx_ = T.xb[mode].coef();
     a.rdiag = T.x[mode].rdiag;
-    a.roff = T.x[mode].roff;
     fill_so(a, *g, mode);
     a.so_y = 0;
     return a;
@@ -448,7 +445,6 @@ static YArgs<R> y_args(ssgp_grid g, int mode, void *psi, double *partials) {
     a.plane = plane_of(*g);
     a.cy = T.y[mode].coef();
     a.rdiag = T.y[mode].rdiag;
-    a.roff = T.y[mode].roff;
     a.norm_partials = partials;
     return a;
 }
@@ -523,7 +519,6 @@ template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int
     a.m = model<R>(*g, mode, omega);
     a.cx_ = T.x[mode].coef();
     a.rdiag = T.x[mode].rdiag;
-    a.roff = T.x[mode].roff;
     XArgs<R> tmp{};
     fill_so(tmp, *g, mode);
     for (int q = 0; q < 9; ++q) a.qx[q] = tmp.qx[q];

@@ -416,7 +416,7 @@ template <int L> __host__ __device__ constexpr int srow(int n) { return n + n / 
 // y-derivative terms.  A sliding window reads every staged value once.
 template <typename R, int L, int J>
 __device__ __forceinline__ void build_rhs(const cx<R> *s, const cx<R> *ys, int ld, int nx, int start, int len,
-                                          const cx<R> *q, unsigned qmask, cx<R> rdiag, cx<R> roff,
+                                          const cx<R> *q, unsigned qmask, cx<R> rdiag,
                                           cx<R> (&r)[L]) {
     auto at = [&](int jp, int i) -> cx<R> {
         return (i >= 0 && i < nx) ? s[jp * ld + sidx<L>(i)] : czero<R>();
@@ -459,7 +459,7 @@ __device__ __forceinline__ void build_rhs(const cx<R> *s, const cx<R> *ys, int l
         if (t < len) {
             shift_win(start + t + 1);
             const cx<R> un = u_at(start + t + 1);
-            r[t] = cfma(roff, um + un, rdiag * uc);
+            r[t] = cn_rhs(rdiag, uc, um + un);
             um = uc;
             uc = un;
         } else {
@@ -470,11 +470,11 @@ __device__ __forceinline__ void build_rhs(const cx<R> *s, const cx<R> *ys, int l
 
 template <typename R, int L>
 __device__ __forceinline__ void build_rhs_any(int J, const cx<R> *s, const cx<R> *ys, int ld, int nx, int start,
-                                              int len, const cx<R> *q, unsigned qmask, cx<R> rdiag, cx<R> roff,
+                                              int len, const cx<R> *q, unsigned qmask, cx<R> rdiag,
                                               cx<R> (&r)[L]) {
-    if (J == 0) build_rhs<R, L, 0>(s, ys, ld, nx, start, len, q, qmask, rdiag, roff, r);
-    else if (J == 1) build_rhs<R, L, 1>(s, ys, ld, nx, start, len, q, qmask, rdiag, roff, r);
-    else build_rhs<R, L, 2>(s, ys, ld, nx, start, len, q, qmask, rdiag, roff, r);
+    if (J == 0) build_rhs<R, L, 0>(s, ys, ld, nx, start, len, q, qmask, rdiag, r);
+    else if (J == 1) build_rhs<R, L, 1>(s, ys, ld, nx, start, len, q, qmask, rdiag, r);
+    else build_rhs<R, L, 2>(s, ys, ld, nx, start, len, q, qmask, rdiag, r);
 }
 
 // ------------------------------------------------------------- x-pass ---
@@ -488,7 +488,7 @@ template <typename R> struct XArgs {
     const double *dscale;      // RENORM factors to apply first, or nullptr
     int pointwise;             // 1: CALCNU + HERM in this pass
     LineCoef<R> cx_;           // CN_x elimination coefficients (256 chunks of KM points)
-    cx<R> rdiag, roff;         // right-hand side (I - sT): diagonal, off-diagonal
+    cx<R> rdiag;               // diagonal of (I - sT)/o (off-diagonal -1)
     cx<R> qx[9];               // SO: psi'_j += sum_j' qx[j][j'] (psi_j'(i+1) - psi_j'(i-1))
     unsigned qxmask;           // bit 3j+j' set where qx[j][j'] != 0
     int so_y;                  // 1: add qy terms with rows iy +- 1 of src
@@ -778,7 +778,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         for (int k = 0; k < KM; ++k) {
             const cx<R> pu = k > 0 ? u[j][k > 0 ? k - 1 : 0] : ub;
             const cx<R> nu = k + 1 < KM ? u[j][k + 1 < KM ? k + 1 : 0] : ua;
-            r[j][k] = (FULL || i0 + k < nx) ? cfma(a.roff, pu + nu, a.rdiag * u[j][k]) : czero<R>();
+            r[j][k] = (FULL || i0 + k < nx) ? cn_rhs(a.rdiag, u[j][k], pu + nu) : czero<R>();
         }
     }
 
@@ -882,7 +882,7 @@ template <typename R> struct YArgs {
     int nx, ny;
     long long plane;
     LineCoef<R> cy;            // CN_y elimination coefficients (blockDim/TX chunks)
-    cx<R> rdiag, roff;
+    cx<R> rdiag;
     double *norm_partials;     // [3][gridDim.x] sums of |psi|^2, or nullptr
 };
 
@@ -909,7 +909,7 @@ __device__ __forceinline__ void ypass_solve(const YArgs<R> &a, const cx<R> *col,
             const cx<R> left = t == 0 ? fl : f[t > 0 ? t - 1 : 0];
             const cx<R> right = FULL ? (t + 1 < L ? f[t + 1 < L ? t + 1 : 0] : fr)
                                      : ((t + 1 < L && t + 1 < len) ? f[t + 1 < L ? t + 1 : 0] : fr);
-            r[t] = cfma(a.roff, left + right, a.rdiag * f[t]);
+            r[t] = cn_rhs(a.rdiag, f[t], left + right);
         } else {
             r[t] = czero<R>();
         }
@@ -1090,7 +1090,7 @@ template <typename R> struct Args1D {
     R dx, x0;
     Model<R> m;
     LineCoef<R> cx_;
-    cx<R> rdiag, roff;
+    cx<R> rdiag;
     cx<R> qx[9];
     unsigned qxmask;
     RenormSpec sp;
@@ -1129,7 +1129,7 @@ __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
         }
         __syncthreads();
         cx<R> r[L];
-        build_rhs_any<R, L>(j, s, nullptr, ld, nx, start, len, a.qx, a.qxmask, a.rdiag, a.roff, r);
+        build_rhs_any<R, L>(j, s, nullptr, ld, nx, start, len, a.qx, a.qxmask, a.rdiag, r);
         __syncthreads();
         solve_line_wave<R, L, CM>(r, start, len, a.cx_);
         if (a.m.imag) {
