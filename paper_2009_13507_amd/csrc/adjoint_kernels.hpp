@@ -159,11 +159,19 @@ template <typename R> struct AdjXArgs {
     double *omega_partials;    // [ny] per-row Omega derivative
 };
 
+// One row per workgroup of ADJ_THREADS: wavefronts 0-2 solve the three
+// CN_x^H lines, all wavefronts share the pointwise part (SO^H and the
+// transposed HERM/CALCNU, the bulk of the arithmetic).
+#ifndef ADJ_THREADS_DEF
+#define ADJ_THREADS_DEF 256
+#endif
+constexpr int ADJ_THREADS = ADJ_THREADS_DEF;
+
 template <typename R, int L, int CM>
-__global__ void __launch_bounds__(ROW_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
+__global__ void __launch_bounds__(ADJ_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
     extern __shared__ unsigned char smem_raw[];
     cx<R> *s = reinterpret_cast<cx<R> *>(smem_raw);
-    __shared__ double red[3];
+    __shared__ double red[ADJ_THREADS / 64];
     const int nx = a.nx;
     const int ld = srow<L>(nx);
     const int row = blockIdx.x;
@@ -172,7 +180,7 @@ __global__ void __launch_bounds__(ROW_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
     cx<R> *lam = a.lam + roff;
     const cx<R> *psi = a.psi_n + roff;
 
-    for (int i = tid; i < nx; i += ROW_THREADS) {
+    for (int i = tid; i < nx; i += ADJ_THREADS) {
         const int si = sidx<L>(i);
         s[si] = lam[i];
         s[ld + si] = lam[a.plane + i];
@@ -180,7 +188,7 @@ __global__ void __launch_bounds__(ROW_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
     }
     __syncthreads();
     // CN_x^H per component
-    {
+    if (tid < 192) {
         const int j = tid >> 6, lane = tid & 63;
         const int start = lane * L;
         const int len = max(0, min(L, nx - start));
@@ -213,7 +221,7 @@ __global__ void __launch_bounds__(ROW_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
     const R yv = a.y0 + R(row) * a.dy;
     const R vy = R(0.5) * a.m.kappa2 * yv * yv;
     double dom = 0.0;
-    for (int i = tid; i < nx; i += ROW_THREADS) {
+    for (int i = tid; i < nx; i += ADJ_THREADS) {
         cx<R> g[3], p[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -238,7 +246,11 @@ __global__ void __launch_bounds__(ROW_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
     for (int d = 32; d >= 1; d >>= 1) dom += __shfl_down(dom, d, 64);
     if ((tid & 63) == 0) red[tid >> 6] = dom;
     __syncthreads();
-    if (tid == 0) a.omega_partials[row] = red[0] + red[1] + red[2];
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < ADJ_THREADS / 64; ++w) t += red[w];
+        a.omega_partials[row] = t;
+    }
 }
 
 } // namespace ssgp
