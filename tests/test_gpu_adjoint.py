@@ -48,7 +48,7 @@ def start(dim, nx, ny, dx, seed):
     return base * (1 + W.random_state(base.shape, seed, 0.05))
 
 
-@pytest.mark.parametrize("dim,nx,ny", [(2, 40, 33), (2, 130, 70), (1, 200, 1)])
+@pytest.mark.parametrize("dim,nx,ny", [(2, 40, 33), (2, 130, 70), (2, 300, 17), (1, 200, 1), (1, 600, 1)])
 def test_adjoint_steps_match_oracle(dim, nx, ny):
     dx = 0.3 if dim == 2 else 0.1
     base = base_cfg(dim, nx, ny, dx)
