@@ -115,6 +115,34 @@ def adjoint_ratio(reps: int = 2):
             "grad_omega_first": float(om.grad[0])}
 
 
+def imag_workloads():
+    """The two imaginary-time workloads: the 1D run (512 points, 20000 steps,
+    the whole state in one workgroup's LDS) in full, and the 2D 256^2 SO +
+    Rabi run over its first 2000 steps; steps/s, grid-point-steps/s and the
+    energy reached."""
+    import torch
+
+    from paper_2009_13507_amd import api
+    from paper_2009_13507_amd import workloads as W
+
+    out = {}
+    for w, psi0, steps in ((W.W1D, W.initial_1d(), W.W1D.steps), (W.W2D_IMAG, W.initial_2d_imag(), 2000)):
+        state = torch.from_numpy(psi0).to("cuda:0")
+        g = api.Grid(state, w.dx, w.dy if w.dim == 2 else None)
+        g.set_params(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, dt=w.dt, so=w.so)
+        g.step_imag(20)  # warm-up (tables, code objects)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step_imag(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        o = g.observables()
+        g.close()
+        out[w.name] = {"steps": steps, "steps_per_s": steps / el, "pt_steps_per_s": w.npts * steps / el,
+                       "ms_per_step": 1e3 * el / steps, "E": o["E"], "N": o["N"]}
+    return out
+
+
 def batch_compare(steps: int = 200, warmup: int = 20):
     """The 64-instance imaginary-time batch (sizes 128..512, seed-1 draw):
     batched (autotuned launch shape, graph replay) against one grid at a
@@ -273,6 +301,7 @@ def main():
         line["adjoint_cost_ratio"] = adjoint_ratio()
     if not args.no_batch:
         line["batch_c4"] = batch_compare()
+        line["imag_workloads"] = imag_workloads()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, psi0, args.cpu_seconds)
     print(json.dumps(line), flush=True)
