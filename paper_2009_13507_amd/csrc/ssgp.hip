@@ -462,11 +462,12 @@ template <typename R> static int adjoint_steps(ssgp_grid g, const void *states, 
 static int ew_blocks(long long n) { return (int)std::min<long long>((n + 255) / 256, 2048); }
 
 // One 2D step from src into dst (dst may equal src except with a
-// y-derivative SO form).  Imaginary time: dscale are the RENORM factors of
-// the previous step (nullptr for none); the norms of the result are reduced
-// into g->renorm.
+// y-derivative SO form).  Imaginary time: with renorm_prev the RENORM of the
+// previous step (whose y-pass left its tile partials in g->partials) is
+// applied first, reduced inside the x-pass; the y-pass leaves this step's
+// partials.
 template <typename R>
-static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omega, const double *dscale) {
+static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omega, bool renorm_prev) {
     const bool imag = mode == MODE_IMAG;
     hipEvent_t *ev = nullptr;
     if (g->prof_every > 0 && (g->prof_counter++ % g->prof_every) == 0 && g->prof_used < g->prof_cap)
@@ -489,22 +490,28 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
         pa.x0 = (R)(-0.5 * g->nx * g->dx);
         pa.y0 = (R)(-0.5 * g->ny * g->dy);
         pa.m = model<R>(*g, mode, omega);
-        pa.dscale = dscale;
+        pa.dscale = nullptr;
+        if (renorm_prev) {
+            LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), ntiles, renorm_spec(*g),
+                                              g->renorm.as<double>()));
+            pa.dscale = g->renorm.as<double>();
+        }
         LAUNCH_TRY(launch_pointwise<R>(lc(*g), pa, ew_blocks(pa.plane)));
         XArgs<R> xa = x_args<R>(g, mode, g->scratch.p, dst, omega, nullptr);
         xa.pointwise = 0;
         xa.so_y = 1;
         SSGP_TRY(launch_x<R>(*g, xa, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     } else {
-        XArgs<R> xa = x_args<R>(g, mode, src, dst, omega, dscale);
+        XArgs<R> xa = x_args<R>(g, mode, src, dst, omega, nullptr);
+        if (renorm_prev) {
+            xa.rpart = g->partials.as<double>();
+            xa.rntiles = ntiles;
+            xa.rsp = renorm_spec(*g);
+        }
         SSGP_TRY(launch_x<R>(*g, xa, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     }
     YArgs<R> ya = y_args<R>(g, mode, dst, imag ? g->partials.as<double>() : nullptr);
     SSGP_TRY(launch_y<R>(*g, ya, ys, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
-    if (imag) {
-        LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), ntiles, renorm_spec(*g),
-                                          g->renorm.as<double>()));
-    }
     return SSGP_OK;
 }
 
@@ -532,9 +539,11 @@ template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int
 template <typename R> static int step_imag_t(ssgp_grid g, int nsteps) {
     SSGP_TRY(build_tables<R>(g, MODE_IMAG));
     if (g->dim == 1) return launch_1d<R>(g, MODE_IMAG, g->psi, nsteps, g->p.omega);
-    for (int s = 0; s < nsteps; ++s)
-        SSGP_TRY(step2d<R>(g, MODE_IMAG, g->psi, g->psi, g->p.omega, s == 0 ? nullptr : g->renorm.as<double>()));
+    for (int s = 0; s < nsteps; ++s) SSGP_TRY(step2d<R>(g, MODE_IMAG, g->psi, g->psi, g->p.omega, s > 0));
     if (nsteps > 0) {
+        // the last step's RENORM
+        LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), (g->nx + YTX - 1) / YTX,
+                                          renorm_spec(*g), g->renorm.as<double>()));
         LAUNCH_TRY(launch_scale<R>(lc(*g), static_cast<cx<R> *>(g->psi), plane_of(*g), g->renorm.as<double>(),
                                    ew_blocks(plane_of(*g))));
     }
@@ -569,7 +578,7 @@ template <typename R> static int step_real_t(ssgp_grid g, const void *src, void 
     const cx<R> *cur = static_cast<const cx<R> *>(src);
     for (int s = 0; s < nsteps; ++s) {
         cx<R> *out = static_cast<cx<R> *>(dst) + (seq ? (size_t)s * state_elems : 0);
-        SSGP_TRY(step2d<R>(g, MODE_REAL, cur, out, omega_at(*g, g->step_index), nullptr));
+        SSGP_TRY(step2d<R>(g, MODE_REAL, cur, out, omega_at(*g, g->step_index), false));
         g->step_index += 1;
         cur = out;
     }

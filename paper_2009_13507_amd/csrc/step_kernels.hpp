@@ -478,6 +478,37 @@ __device__ __forceinline__ void build_rhs_any(int J, const cx<R> *s, const cx<R>
 }
 
 // ------------------------------------------------------------- x-pass ---
+// ------------------------------------------------ RENORM on the device ---
+// Rescaling factors of App. A: Eq. (DJ) keeps N = 1 and N_{+1} - N_{-1} = m,
+// Eq. (DJ2) keeps N = 1 only.
+struct RenormSpec {
+    int fixed_m;   // 1: Eq. (DJ) (with the fall-backs), 0: Eq. (DJ2)
+    double m;
+    double dA;
+};
+
+__device__ __forceinline__ void renorm_factors(const RenormSpec &sp, const double N[3], double d[3],
+                                               double *fallback) {
+    const double Np = N[0], N0 = N[1], Nm = N[2];
+    if (sp.fixed_m) {
+        const double m = sp.m;
+        if (fabs(m) < 1.0 && Np > 0.0 && Nm > 0.0) {
+            const double d0 = sqrt(1.0 - m * m) / sqrt(N0 + sqrt(4.0 * (1.0 - m * m) * Np * Nm + m * m * N0 * N0));
+            const double rp = 1.0 + m - d0 * d0 * N0, rm = 1.0 - m - d0 * d0 * N0;
+            if (rp >= 0.0 && rm >= 0.0) {
+                d[0] = sqrt(rp) / sqrt(2.0 * Np);
+                d[1] = d0;
+                d[2] = sqrt(rm) / sqrt(2.0 * Nm);
+                *fallback = 0.0;
+                return;
+            }
+        }
+        *fallback = 1.0;
+    }
+    const double dd = 1.0 / sqrt(N0 + Np + Nm);
+    d[0] = d[1] = d[2] = dd;
+}
+
 template <typename R> struct XArgs {
     const cx<R> *src;          // state read (3 planes)
     cx<R> *dst;                // state written (may equal src unless so_y)
@@ -486,6 +517,9 @@ template <typename R> struct XArgs {
     R dx, dy, x0, y0;
     Model<R> m;
     const double *dscale;      // RENORM factors to apply first, or nullptr
+    const double *rpart;       // or: the previous y-pass's tile partials [3][rntiles],
+    int rntiles;               //     reduced here into the factors (rsp: the rule)
+    RenormSpec rsp;
     int pointwise;             // 1: CALCNU + HERM in this pass
     LineCoef<R> cx_;           // CN_x elimination coefficients (256 chunks of KM points)
     cx<R> rdiag;               // diagonal of (I - sT)/o (off-diagonal -1)
@@ -582,6 +616,8 @@ __device__ __forceinline__ void wave_scan_down3(cx<R> (&A)[3], cx<R> (&B)[3], in
 // row has exactly 256 KM points, so no point needs a range check.  SOY: the
 // SO form has y derivatives (terms with rows iy +- 1 of src).
 template <typename R, int KM> struct XShared {
+    double red[3][XPASS_THREADS];      // RENORM reduction of the tile partials
+    double d[3];                       // RENORM factors
     cx<R> E[2 * 24];                   // edges: [round][4 waves][2 ends][3 comps]
     cx<R> scA[2][4][3], scB[2][4][3];  // wavefront maps: [sweep][wave][comp]
     cx<R> xch[4][KM > 1 ? 64 * KM + 64 : 1];  // per-wavefront store line (see store_row)
@@ -671,12 +707,37 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     const cx<R> *src = a.src + roff;
 
     // ---- RENORM scale, CALCNU + HERM
+    if (a.rpart) {
+        // the factors from the previous step's tile partials: the same
+        // fixed-order sums as renorm_finalize_kernel, in every workgroup
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double t = 0.0;
+            for (int q = tid; q < a.rntiles; q += XPASS_THREADS) t += a.rpart[(long long)j * a.rntiles + q];
+            sh.red[j][tid] = t;
+        }
+        __syncthreads();
+        for (int wd = XPASS_THREADS / 2; wd >= 1; wd >>= 1) {
+            if (tid < wd)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) sh.red[j][tid] += sh.red[j][tid + wd];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const double N[3] = {sh.red[0][0] * a.rsp.dA, sh.red[1][0] * a.rsp.dA, sh.red[2][0] * a.rsp.dA};
+            double fb = 0.0;
+            renorm_factors(a.rsp, N, sh.d, &fb);
+        }
+        __syncthreads();
+    }
     {
+        const bool scale = a.dscale || a.rpart;
+        const double *ds = a.rpart ? sh.d : a.dscale;
         R d0 = R(1), d1 = R(1), d2 = R(1);
-        if (a.dscale) {
-            d0 = R(a.dscale[0]);
-            d1 = R(a.dscale[1]);
-            d2 = R(a.dscale[2]);
+        if (scale) {
+            d0 = R(ds[0]);
+            d1 = R(ds[1]);
+            d2 = R(ds[2]);
         }
         const R yv = a.y0 + R(row) * a.dy;
         const R vy = R(0.5) * a.m.kappa2 * yv * yv;
@@ -684,7 +745,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         for (int k = 0; k < KM; ++k) {
             const int i = i0 + k;
             if (FULL || i < nx) {
-                if (a.dscale) {
+                if (scale) {
                     v[0][k] = d0 * v[0][k];
                     v[1][k] = d1 * v[1][k];
                     v[2][k] = d2 * v[2][k];
@@ -1036,37 +1097,6 @@ __global__ void __launch_bounds__(256) pointwise_kernel(PArgs<R> a) {
         a.psi[n + q] = z;
         a.psi[2 * n + q] = m;
     }
-}
-
-// ------------------------------------------------ RENORM on the device ---
-// Rescaling factors of App. A: Eq. (DJ) keeps N = 1 and N_{+1} - N_{-1} = m,
-// Eq. (DJ2) keeps N = 1 only.
-struct RenormSpec {
-    int fixed_m;   // 1: Eq. (DJ) (with the fall-backs), 0: Eq. (DJ2)
-    double m;
-    double dA;
-};
-
-__device__ __forceinline__ void renorm_factors(const RenormSpec &sp, const double N[3], double d[3],
-                                               double *fallback) {
-    const double Np = N[0], N0 = N[1], Nm = N[2];
-    if (sp.fixed_m) {
-        const double m = sp.m;
-        if (fabs(m) < 1.0 && Np > 0.0 && Nm > 0.0) {
-            const double d0 = sqrt(1.0 - m * m) / sqrt(N0 + sqrt(4.0 * (1.0 - m * m) * Np * Nm + m * m * N0 * N0));
-            const double rp = 1.0 + m - d0 * d0 * N0, rm = 1.0 - m - d0 * d0 * N0;
-            if (rp >= 0.0 && rm >= 0.0) {
-                d[0] = sqrt(rp) / sqrt(2.0 * Np);
-                d[1] = d0;
-                d[2] = sqrt(rm) / sqrt(2.0 * Nm);
-                *fallback = 0.0;
-                return;
-            }
-        }
-        *fallback = 1.0;
-    }
-    const double dd = 1.0 / sqrt(N0 + Np + Nm);
-    d[0] = d[1] = d[2] = dd;
 }
 
 template <typename R>
