@@ -295,8 +295,24 @@ struct GridCore {
     int prof_every = 0, prof_cap = 0, prof_used = 0;
     long long prof_counter = 0;
     std::vector<hipEvent_t> prof_events;
+    // runs of 2D steps replayed as HIP graphs (captured on a private stream,
+    // launched on the grid's stream), keyed by everything baked into them
+    struct StepGraph {
+        int mode, k, renorm_first;
+        const void *psi;
+        double omega;
+        hipGraphExec_t exec;
+    };
+    std::vector<StepGraph> graphs;
+    hipStream_t cap = nullptr;
+    void clear_graphs() {
+        for (StepGraph &x : graphs) (void)hipGraphExecDestroy(x.exec);
+        graphs.clear();
+    }
     ~GridCore() {
         for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
+        clear_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
     }
 };
 
@@ -329,6 +345,7 @@ template <> Tables<float> &tables<float>(ssgp_grid g) { return g->t32; }
 
 template <typename R> static int build_tables(ssgp_grid g, int mode) {
     if (g->built_mode_mask & (1 << mode)) return SSGP_OK;
+    g->clear_graphs();  // the graphs hold pointers into the tables
     Tables<R> &T = tables<R>(g);
     const cd s = cn_s(mode, g->p.dt);
     const int Lx = x_chunk(g->nx);
@@ -469,6 +486,7 @@ static int ew_blocks(long long n) { return (int)std::min<long long>((n + 255) / 
 template <typename R>
 static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omega, bool renorm_prev) {
     const bool imag = mode == MODE_IMAG;
+    renorm_prev = renorm_prev && imag;
     hipEvent_t *ev = nullptr;
     if (g->prof_every > 0 && (g->prof_counter++ % g->prof_every) == 0 && g->prof_used < g->prof_cap)
         ev = &g->prof_events[(size_t)4 * g->prof_used++];
@@ -515,6 +533,76 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
     return SSGP_OK;
 }
 
+// Longest run of steps replayed as one graph.
+constexpr int STEP_GRAPH_MAX = 64;
+
+template <typename R>
+static int step_graph(ssgp_grid g, int mode, int k, bool renorm_first, double omega, hipGraphExec_t *out) {
+    for (const GridCore::StepGraph &x : g->graphs)
+        if (x.mode == mode && x.k == k && x.renorm_first == (int)renorm_first && x.psi == g->psi && x.omega == omega) {
+            *out = x.exec;
+            return SSGP_OK;
+        }
+    if (g->graphs.size() >= 32) g->clear_graphs();
+    if (!g->cap) HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+    // capture on the private stream with kernel timing off
+    const hipStream_t saved = g->stream;
+    const int saved_every = g->prof_every;
+    g->stream = g->cap;
+    g->prof_every = 0;
+    int rc = SSGP_OK;
+    hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int s = 0; s < k && rc == SSGP_OK; ++s)
+            rc = step2d<R>(g, mode, g->psi, g->psi, omega, mode == MODE_IMAG && (renorm_first || s > 0));
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(g->cap, &graph);
+        if (e == hipSuccess && rc == SSGP_OK) {
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e == hipSuccess) {
+                g->graphs.push_back({mode, k, (int)renorm_first, g->psi, omega, exec});
+                *out = exec;
+            }
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    g->stream = saved;
+    g->prof_every = saved_every;
+    SSGP_TRY(rc);
+    if (e != hipSuccess) return fail(SSGP_EDEVICE, "step graph capture failed: %s", hipGetErrorString(e));
+    return SSGP_OK;
+}
+
+// n in-place 2D steps of g->psi at a fixed Omega.  Runs of steps go out as
+// graph replays (runs of 2^i <= 64 steps), except steps whose kernels are
+// timed and the y-derivative SO forms (their extra pass copies the state),
+// which are launched one by one.  Imaginary time: every step but (unless
+// renorm_first) the first applies the previous step's RENORM.
+template <typename R> static int run_steps(ssgp_grid g, int mode, int n, double omega, bool renorm_first) {
+    if (mode != MODE_IMAG) renorm_first = false;
+    const bool graphable = g->dim == 2 && !(so_has_y(g->p.so) && g->p.gamma != 0.0);
+    int s = 0;
+    while (s < n) {
+        const bool timing = g->prof_every > 0 && g->prof_used < g->prof_cap;
+        if (!graphable || (timing && g->prof_counter % g->prof_every == 0)) {
+            SSGP_TRY(step2d<R>(g, mode, g->psi, g->psi, omega, mode == MODE_IMAG && (renorm_first || s > 0)));
+            ++s;
+            continue;
+        }
+        int k = n - s;
+        if (timing) k = std::min<long long>(k, g->prof_every - g->prof_counter % g->prof_every);
+        int p = 1;
+        while (p * 2 <= std::min(k, STEP_GRAPH_MAX)) p *= 2;
+        hipGraphExec_t exec = nullptr;
+        SSGP_TRY(step_graph<R>(g, mode, p, mode == MODE_IMAG && (renorm_first || s > 0), omega, &exec));
+        HIP_TRY(hipGraphLaunch(exec, g->stream));
+        if (g->prof_every > 0) g->prof_counter += p;
+        s += p;
+    }
+    return SSGP_OK;
+}
+
 template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int nsteps, double omega) {
     Tables<R> &T = tables<R>(g);
     Args1D<R> a{};
@@ -539,7 +627,7 @@ template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int
 template <typename R> static int step_imag_t(ssgp_grid g, int nsteps) {
     SSGP_TRY(build_tables<R>(g, MODE_IMAG));
     if (g->dim == 1) return launch_1d<R>(g, MODE_IMAG, g->psi, nsteps, g->p.omega);
-    for (int s = 0; s < nsteps; ++s) SSGP_TRY(step2d<R>(g, MODE_IMAG, g->psi, g->psi, g->p.omega, s > 0));
+    SSGP_TRY(run_steps<R>(g, MODE_IMAG, nsteps, g->p.omega, false));
     if (nsteps > 0) {
         // the last step's RENORM
         LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), (g->nx + YTX - 1) / YTX,
@@ -572,6 +660,22 @@ template <typename R> static int step_real_t(ssgp_grid g, const void *src, void 
             g->step_index += chunk;
             done += chunk;
             cur = out;
+        }
+        return SSGP_OK;
+    }
+    if (!seq && src == g->psi && dst == g->psi) {
+        // in place: runs of steps at one Omega
+        int done = 0;
+        while (done < nsteps) {
+            int chunk = nsteps - done;
+            if (!g->omega_sched.empty()) {
+                const long long n = g->step_index;
+                const long long seg_end = (n / g->steps_per_seg + 1) * g->steps_per_seg;
+                chunk = (int)std::min<long long>(chunk, seg_end - n);
+            }
+            SSGP_TRY(run_steps<R>(g, MODE_REAL, chunk, omega_at(*g, g->step_index), false));
+            g->step_index += chunk;
+            done += chunk;
         }
         return SSGP_OK;
     }
@@ -653,6 +757,7 @@ extern "C" int ssgp_create_grid(int dim, int nx, int ny, double dx, double dy, i
 extern "C" int ssgp_set_state(ssgp_grid g, void *psi_dev) {
     if (!g || !psi_dev) return fail(SSGP_EINVAL, "NULL argument");
     g->psi = psi_dev;
+    g->clear_graphs();
     return SSGP_OK;
 }
 
@@ -660,6 +765,7 @@ extern "C" int ssgp_set_params(ssgp_grid g, const ssgp_params *p) {
     if (!g) return fail(SSGP_EINVAL, "grid is NULL");
     SSGP_TRY(check_params(*g, p));
     if (!g->have_params || p->dt != g->p.dt) g->built_mode_mask = 0;
+    g->clear_graphs();  // the graphs hold the model constants
     g->p = *p;
     g->have_params = true;
     return SSGP_OK;
@@ -671,6 +777,7 @@ extern "C" int ssgp_set_omega_schedule(ssgp_grid g, const double *omega, int nse
     for (int s = 0; s < nseg; ++s)
         if (!std::isfinite(omega[s])) return fail(SSGP_EINVAL, "non-finite Omega");
     g->omega_sched.assign(omega, omega + nseg);
+    g->clear_graphs();
     g->steps_per_seg = nseg > 0 ? steps_per_seg : 1;
     const size_t n = std::max(1, nseg);
     SSGP_TRY(g->omega_acc.ensure(sizeof(double) * n));
