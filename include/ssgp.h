@@ -127,10 +127,15 @@ int ssgp_set_step_index(ssgp_grid g, long long n);
 long long ssgp_get_step_index(ssgp_grid g);
 
 /* nsteps >= 0 full imaginary-time steps on the bound state, in place;
- * RENORM after every step; the state is normalised on return. */
+ * RENORM after every step; the state is normalised on return.  On 2D grids
+ * runs of steps are enqueued as HIP graph replays (captured once per run
+ * length on a library-owned stream, launched on the grid's stream; kernel-
+ * timed steps and the y-derivative SO forms are launched one by one); the
+ * stream ordering is the same either way. */
 int ssgp_step_imag(ssgp_grid g, int nsteps);
 
-/* nsteps >= 0 full real-time steps on the bound state, in place. */
+/* nsteps >= 0 full real-time steps on the bound state, in place (graph
+ * replays as for ssgp_step_imag, split where the Omega schedule changes). */
 int ssgp_step_real(ssgp_grid g, int nsteps);
 
 /* nsteps real-time steps starting from src_dev, writing the state after step
