@@ -94,3 +94,20 @@ def test_graph_runs_match_oracle(imag, calls):
         got = t.cpu().numpy()
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10, n
     g.close()
+
+
+@pytest.mark.parametrize("every,capacity", [(5, 1000), (7, 3)])
+def test_sampled_timing_mixes_graphs_and_single_steps(every, capacity):
+    """Kernel timing on every few steps (and a capacity that runs out) splits
+    the runs around the timed steps; the result stays bitwise equal."""
+    (ge, te), (gg, tg) = pair(96, 64, 0.25, c0=2.0, c2=0.1, gamma=0.8, omega=0.2, dt=1e-3, so=api.SO_PX_SX)
+    gg.profile(every, capacity)
+    for n in (37, 20):
+        ge.step_real(n)
+        gg.step_real(n)
+        assert same(te, tg), n
+    p = gg.profile_read()
+    # steps 0 .. 56 of the counter; every every-th one is timed, up to capacity
+    assert p["steps"] == min(capacity, len(range(0, 57, every)))
+    ge.close()
+    gg.close()
