@@ -306,6 +306,8 @@ struct GridCore {
     std::vector<StepGraph> graphs;
     hipStream_t cap = nullptr;
     void clear_graphs() {
+        if (graphs.empty()) return;
+        (void)hipStreamSynchronize(stream);  // no replay of them still in flight
         for (StepGraph &x : graphs) (void)hipGraphExecDestroy(x.exec);
         graphs.clear();
     }
