@@ -42,7 +42,8 @@ def start_state(dim, nx, ny, dx, dy, seed=0):
     return base * (1 + noise)
 
 
-SHAPES_2D = [(96, 80), (37, 29), (130, 67), (64, 64), (1, 7), (5, 1), (200, 3), (513, 33)]
+SHAPES_2D = [(96, 80), (37, 29), (130, 67), (64, 64), (1, 7), (5, 1), (200, 3), (513, 33),
+             (256, 20), (512, 9), (1024, 5), (2048, 3), (1500, 4), (3, 2048), (5, 1500)]
 
 
 @pytest.mark.parametrize("nx,ny", SHAPES_2D)
@@ -157,10 +158,11 @@ def test_2d_real_workload_grid():
             assert abs(obs[k] - oref[k]) < TOL * abs(oref[k]), k
 
 
-def test_complex64_error_against_fp64_oracle():
+@pytest.mark.parametrize("nx,ny", [(128, 128), (1024, 8), (2048, 4), (700, 9), (6, 1024)])
+def test_complex64_error_against_fp64_oracle(nx, ny):
     """complex64 storage and arithmetic (coefficients from FP64, FP64 norms):
     the stated error after 200 steps is below 1e-5 relative L2."""
-    nx, ny, dx = 128, 128, 0.1
+    dx = 0.1
     p = dict(c0=2.0, c2=-0.1, gamma=0.5, omega=0.1, dt=2.5e-3, so=api.SO_PX_SX)
     psi0 = W.gaussian(2, nx, ny, dx, dx, phases=(0.3, 1.1, 2.0))
     for imag in (True, False):
