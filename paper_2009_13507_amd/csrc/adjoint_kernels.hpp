@@ -159,13 +159,11 @@ template <typename R> struct AdjXArgs {
     double *omega_partials;    // [ny] per-row Omega derivative
 };
 
-// One row per workgroup of ADJ_THREADS: wavefronts 0-2 solve the three
-// CN_x^H lines, all wavefronts share the pointwise part (SO^H and the
-// transposed HERM/CALCNU, the bulk of the arithmetic).
-#ifndef ADJ_THREADS_DEF
-#define ADJ_THREADS_DEF 256
-#endif
-constexpr int ADJ_THREADS = ADJ_THREADS_DEF;
+// One row per workgroup of 4 wavefronts: wavefronts 0-2 solve the three
+// CN_x^H lines, all four share the pointwise part (SO^H and the transposed
+// HERM/CALCNU, the bulk of the arithmetic, about 206 VGPRs: 2 wavefronts per
+// SIMD).  Measured faster than 3, 6 or 8 wavefronts per row.
+constexpr int ADJ_THREADS = 256;
 
 template <typename R, int L, int CM>
 __global__ void __launch_bounds__(ADJ_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {

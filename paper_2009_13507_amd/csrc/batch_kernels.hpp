@@ -4,8 +4,10 @@
 // Per step, over all instances of the batch:
 //   X phase, items (instance, row): RENORM scale of the previous step,
 //      CALCNU, HERM, SO, the Crank-Nicolson right-hand side and the x-line
-//      solve of one row (the single-grid x-pass algorithm with the instance's
-//      coefficients; one item per 4-wavefront workgroup);
+//      solve of one row (one item per 4-wavefront workgroup: the pointwise
+//      part in a coalesced layout, then each component line transposed
+//      through LDS into 64 chunks and solved by one wavefront; for rows of at
+//      most 512 points this measured faster than the single-grid row code);
 //   Y phase, items (instance, component, tile of TX columns): the y-line
 //      solve (chunks in registers, chunk scans across the workgroup) and the
 //      tile's sum of |psi|^2;

@@ -2,28 +2,28 @@
 //
 // One step of the spin-1 GP equations (Sec. 3 and App. A of the paper) is
 // two device-wide passes over the state:
-//   x-pass (one workgroup of 3 wavefronts per row): the renormalisation of
-//          the previous imaginary-time step, CALCNU, HERM (pointwise, in the
-//          coalesced row layout), then the row of all three components is
-//          staged in LDS and each wavefront takes one component: the SO
-//          update (x stencil from LDS) builds the Crank-Nicolson right-hand
-//          side, and the x line is solved by a chunked Thomas elimination;
-//   y-pass (one workgroup per tile of 8 columns and one component): the
+//   x-pass (one workgroup of 4 wavefronts per row, KM consecutive points per
+//          thread): the RENORM of the previous imaginary-time step, CALCNU,
+//          HERM, the SO update and the Crank-Nicolson right-hand side, and
+//          the chunked elimination of the three x lines in the same layout;
+//          coalesced stores through a per-wavefront LDS line;
+//   y-pass (one workgroup per tile of 4 columns and one component): the
 //          Crank-Nicolson solve along y, column chunks held in registers, plus
 //          the per-tile sums of |psi|^2 for the imaginary-time RENORM.
+// The 1D kernel keeps a whole 1D run in one workgroup's LDS.
 //
 // Chunked Thomas elimination.  The matrix I + sT of every line is the same
-// Toeplitz tridiagonal, so the elimination pivots are line independent and
-// tabulated on the host: with c'_i the normalised super-diagonal and inv_i
-// the reciprocal pivots, the forward sweep is y_i = inv_i r_i - c'_i y_{i-1}
-// and the back substitution x_i = y_i - c'_i x_{i+1}.  Each lane owns a
-// contiguous chunk of L points.  Both sweeps are first-order linear
-// recurrences with the multiplier -c'_i, so a lane first runs its chunk with
-// zero carry-in, the chunks are joined by an exact scan of the affine maps
-// Y_k = A_k Y_{k-1} + B_k (A_k = prod over the chunk of -c'_i, tabulated),
-// and each lane adds the carried term, propagated through the same
-// recurrence.  No term is truncated: the result is Thomas elimination up to
-// rounding order.
+// Toeplitz tridiagonal, so the pivots are line independent and tabulated on
+// the host: with c'_i = o / m_i (o the off-diagonal, m_i the pivots) the
+// forward sweep is y_i = c'_i (r_i/o - y_{i-1}) and the back substitution
+// x_i = y_i - c'_i x_{i+1}.  Each lane owns a contiguous chunk of points.
+// Both sweeps are first-order linear recurrences with the multiplier -c'_i,
+// so a lane first runs its chunk with zero carry-in, the chunks are joined by
+// a scan of the affine maps Y_k = A_k Y_{k-1} + B_k (A_k = prod over the
+// chunk of -c'_i, tabulated), and each lane adds the carried term.  The scan
+// depth within a wavefront drops carries from chunks so far back that their
+// weight is below 2^-64 (LineCoef::levels); the result is Thomas elimination
+// up to rounding order.
 #pragma once
 #include "cplx.hpp"
 
@@ -531,7 +531,7 @@ template <typename R> struct XArgs {
 };
 
 constexpr int XPASS_THREADS = 256;
-constexpr int ROW_THREADS = 192;  // 1D and adjoint row kernels: 3 wavefronts
+constexpr int ROW_THREADS = 192;  // 1D kernel: 3 wavefronts, one per component line
 
 // Whole-wavefront rotations by one lane (DPP wave_ror:1 / wave_rol:1):
 // ror1 gives lane l the value of lane l-1 (lane 0 gets lane 63), rol1 the
