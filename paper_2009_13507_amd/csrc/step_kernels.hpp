@@ -962,8 +962,17 @@ __device__ __forceinline__ void ypass_solve(const YArgs<R> &a, const cx<R> *col,
     cx<R> f[L];
 #pragma unroll
     for (int t = 0; t < L; ++t) f[t] = (FULL || t < len) ? col[(long long)(start + t) * nx] : czero<R>();
-    const cx<R> fl = (len > 0 && start >= 1) ? col[(long long)(start - 1) * nx] : czero<R>();
-    const cx<R> fr = (len > 0 && start + len < ny) ? col[(long long)(start + len) * nx] : czero<R>();
+    // The rows just outside the chunk are the last row of chunk k - 1 and the
+    // first row of chunk k + 1, held by lanes tid - TX and tid + TX (whenever
+    // they are needed, those chunks are full and their lanes launched: the
+    // workgroup is whole wavefronts of chunks covering ny).  Only the lanes at
+    // the ends of a wavefront load them, issued with the chunk's own loads.
+    const bool hl = len > 0 && start >= 1, hr = len > 0 && start + len < ny;
+    const cx<R> el = (hl && lane < TX) ? col[(long long)(start - 1) * nx] : czero<R>();
+    const cx<R> er = (hr && lane >= 64 - TX) ? col[(long long)(start + len) * nx] : czero<R>();
+    const cx<R> up = shfl_up(f[L - 1], TX), dn = shfl_down(f[0], TX);
+    const cx<R> fl = hl ? (lane >= TX ? up : el) : czero<R>();
+    const cx<R> fr = hr ? (lane < 64 - TX ? dn : er) : czero<R>();
 #pragma unroll
     for (int t = 0; t < L; ++t) {
         if (FULL || t < len) {
