@@ -11,7 +11,9 @@ States are numpy ``complex128`` arrays of shape ``(3, ny, nx)`` (2D) or
 point), the same for y.
 
 The imaginary-time runs start from a Gaussian trial state, which is the
-paper's choice when the ground state has no vortex or stripe (Sec. 3).
+paper's choice when the ground state has no vortex or stripe (Sec. 3); the
+vortex and stripe trial states of SO-coupled 2D condensates, and the rule that
+picks one of them, are here too.
 """
 from __future__ import annotations
 
@@ -99,6 +101,70 @@ def gaussian(dim: int, nx: int, ny: int, dx: float, dy: float,
         dA = dx * dy
     psi = np.stack([np.sqrt(w) * np.exp(1j * th) * g for w, th in zip(weights, phases)])
     return normalise(psi.astype(np.complex128), dA)
+
+
+def vortex(nx: int, ny: int, dx: float, dy: float, lz=(0, 0, 0),
+           weights=(0.25, 0.5, 0.25), width: float = 1.0):
+    """2D Gaussian trial state with a vortex of angular momentum L_j imprinted
+    on component j (Sec. 3): psi_j is multiplied by (x + iy)^L_j, or by
+    (x - iy)^|L_j| for an anti-vortex (L_j < 0).  Total norm 1."""
+    x = coords(nx, dx)
+    y = coords(ny, dy)
+    X, Y = x[None, :], y[:, None]
+    g = np.exp(-(X ** 2 + Y ** 2) / (2 * width ** 2))
+    comps = []
+    for w, L in zip(weights, lz):
+        z = X + 1j * Y if L >= 0 else X - 1j * Y
+        comps.append(np.sqrt(w) * g * z ** abs(int(L)))
+    return normalise(np.stack(comps).astype(np.complex128), dx * dy)
+
+
+def stripes(nx: int, ny: int, dx: float, dy: float, gamma: float, width: float = 1.0):
+    """2D Gaussian trial state with a stripe modulation along x (Sec. 3): the
+    Gaussian times the polar stripe spinor of Sec. S.2, i sin(gamma x)/sqrt(2)
+    in the +-1 components and -cos(gamma x) in the 0 component.  Total norm 1."""
+    x = coords(nx, dx)
+    y = coords(ny, dy)
+    g = np.exp(-(x[None, :] ** 2 + y[:, None] ** 2) / (2 * width ** 2))
+    sp = 1j * np.sin(gamma * x)[None, :] / np.sqrt(2.0) * g
+    c0 = -np.cos(gamma * x)[None, :] * g
+    return normalise(np.stack([sp, c0, sp]).astype(np.complex128), dx * dy)
+
+
+OPT_ST = 0.75
+
+
+def so_trial_kind(so: int, gamma: float, c2: float, opt_st: float = OPT_ST):
+    """The 2D trial-state rule of Sec. 3, as ("gaussian", None), ("vortex",
+    (L_+1, L_0, L_-1)) or ("stripes", None).
+
+    Polar (c2 > 0) below opt_st: (-1, 0, +1) under Rashba coupling, (+1, 0, -1)
+    under Dresselhaus; above opt_st: stripes.  Ferro (c2 <= 0): (0, +1, +2)
+    under Rashba, (0, -1, -2) under Dresselhaus.  The equal mixture takes a
+    Gaussian in the ferro phase and stripes in the polar phase.  Without a 2D
+    SO coupling the trial state is a Gaussian."""
+    polar = c2 > 0
+    if gamma == 0.0 or so not in (SO_RASHBA, SO_DRESSELHAUS, SO_ERD):
+        return "gaussian", None
+    if so == SO_ERD:
+        return ("stripes", None) if polar else ("gaussian", None)
+    sign = 1 if so == SO_RASHBA else -1
+    if polar:
+        if gamma > opt_st:
+            return "stripes", None
+        return "vortex", (-sign, 0, sign)
+    return "vortex", (0, sign, 2 * sign)
+
+
+def so_trial(nx: int, ny: int, dx: float, dy: float, so: int, gamma: float, c2: float,
+             opt_st: float = OPT_ST, width: float = 1.0, weights=(0.25, 0.5, 0.25)):
+    """The 2D trial state that so_trial_kind selects."""
+    kind, lz = so_trial_kind(so, gamma, c2, opt_st)
+    if kind == "vortex":
+        return vortex(nx, ny, dx, dy, lz, weights, width)
+    if kind == "stripes":
+        return stripes(nx, ny, dx, dy, gamma, width)
+    return gaussian(2, nx, ny, dx, dy, weights=weights, width=width)
 
 
 def phases_seed0():

@@ -6,7 +6,8 @@ Table 4, "spinor" column: ground-state energies at fixed magnetisation m
 (fixed-m RENORM of Eq. (DJ) for m != 0), printed to four decimals: tolerance
 1e-4.  Table 3, gamma p_x Sigma_x with gamma = 0.5 at DX <= 0.2: five
 decimals, tolerance 5e-5.  Initial states are Gaussians with the listed
-component weights."""
+component weights, or, for the 2D SO-coupled entries, the vortex trial states
+of Sec. 3."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -92,3 +93,43 @@ def test_table4_2d_energies(name, c0, c2, gamma, so, m, wts, steps, printed):
     g.close()
     assert abs(o["E"] - printed) < 1e-4, (name, o["E"])
     assert abs(o["M"] - m) < 1e-10
+
+
+# Quasi-2D SO-coupled entries of Tables 3 and 4 (gamma = 0.5, DX = DY = 0.1,
+# DT = 0.0005) from the vortex trial states of Sec. 3, which keep the circular
+# symmetry the paper restricts the 2D states to: (0, +1, +2) in the ferro phase
+# under Rashba coupling, (-1, 0, +1) in the polar phase, and the mirror images
+# under Dresselhaus coupling.  The ferro state settles at the magnetisation the
+# paper lists with it (m = 0.0468, free under the norm-only RENORM); from a
+# Gaussian start the ferro relaxation leaves that symmetry and goes lower.
+# Printed energies: Table 3 at DX = 0.1 (five decimals); tolerance 1e-4.
+TABLE34_2D_SO = [  # (name, c0, c2, so, steps, printed E, printed m)
+    ("ferro Rashba", 1327.5, -6.15, api.SO_RASHBA, 180000, 13.59761, 0.0468),
+    ("ferro Dresselhaus", 1327.5, -6.15, api.SO_DRESSELHAUS, 180000, 13.59761, 0.0468),
+    ("polar Rashba", 482.0, 15.0, api.SO_RASHBA, 100000, 8.19690, 0.0),
+    ("polar Dresselhaus", 482.0, 15.0, api.SO_DRESSELHAUS, 100000, 8.19690, 0.0),
+]
+
+
+@pytest.mark.parametrize("name,c0,c2,so,steps,printed,m", TABLE34_2D_SO, ids=[t[0] for t in TABLE34_2D_SO])
+def test_2d_so_coupled_energies_from_vortex_trial_states(name, c0, c2, so, steps, printed, m):
+    from paper_2009_13507_amd import outputs as O
+    n, dx = 256, 0.1
+    kind, lz = W.so_trial_kind(so, 0.5, c2)
+    assert kind == "vortex"
+    t = torch.from_numpy(W.so_trial(n, n, dx, dx, so, 0.5, c2, width=2.0)).to("cuda:0")
+    g = api.Grid(t, dx, dx)
+    g.set_params(c0=c0, c2=c2, gamma=0.5, so=so, dt=5e-4)
+    done = 0
+    while done < steps:
+        g.step_imag(20000)
+        done += 20000
+        o = g.observables()
+        print(f"  {done} steps: E = {o['E']:.8f}, M = {o['M']:.6f}", flush=True)
+    psi = t.cpu().numpy()
+    g.close()
+    assert abs(o["E"] - printed) < 1e-4, (name, o["E"])
+    assert abs(o["M"] - m) < 1e-3, (name, o["M"])
+    assert abs(o["N"] - 1.0) < 1e-12
+    # the vortex structure of the trial state survives the relaxation
+    assert [O.winding(psi[j], 20) for j in range(3)] == list(lz)
