@@ -211,3 +211,69 @@ def step_adjoint(cfg: Cfg, psi_n, lam):
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+# ------------------------------------------- unitary-SO scheme (opt-in) --
+# Beyond the paper: the SO term of Eqs. (p1)-(p2) is taken by Crank-Nicolson
+# together with LUX (Table 1), so a real-time step stays unitary for
+# gamma != 0.  Written from the definition: for every x line,
+#   (I + s H) psi' = (I - s H) psi,  H = I_3 (x) T + gamma S_a (x) (-i D),
+# T = -1/2 d^2/dx^2 and D = d/dx by the three-point and central stencils with
+# zero ghosts, S_a the spin-1 matrix of Eq. (3) of the p_x Sigma_a form, and
+# s = i dt/2 in real time, dt/2 in imaginary time (Delta -> -i Delta).  The
+# line vector is component-major (psi_{+1}(x_0..), psi_0(..), psi_{-1}(..)).
+
+SCHEME_PAPER, SCHEME_UNITARY_SO = range(2)
+
+_S2 = np.sqrt(2.0)
+_SPIN = {  # Eq. (3)
+    SO_PX_SX: np.array([[0, 1, 0], [1, 0, 1], [0, 1, 0]], dtype=complex) / _S2,
+    SO_PX_SY: 1j * np.array([[0, -1, 0], [1, 0, -1], [0, 1, 0]], dtype=complex) / _S2,
+    SO_PX_SZ: np.diag([1.0, 0.0, -1.0]).astype(complex),
+}
+
+
+def _line_hamiltonian(cfg: Cfg):
+    """H of one x line (sparse, 3 nx x 3 nx) for the x-derivative SO forms."""
+    import scipy.sparse as sp
+    n, h = cfg.nx, cfg.dx
+    T = sp.diags([np.full(n - 1, -0.5 / h ** 2), np.full(n, 1.0 / h ** 2), np.full(n - 1, -0.5 / h ** 2)],
+                 [-1, 0, 1])
+    D = sp.diags([np.full(n - 1, -0.5 / h), np.full(n - 1, 0.5 / h)], [-1, 1])
+    H = sp.kron(sp.identity(3), T)
+    if cfg.so != SO_NONE and cfg.gamma != 0.0:
+        if cfg.so not in _SPIN:
+            raise ValueError("the unitary-SO scheme takes the p_x Sigma_a forms")
+        H = H + sp.kron(cfg.gamma * _SPIN[cfg.so], -1j * D)
+    return sp.csc_matrix(H, dtype=complex)
+
+
+def cn_x_so(cfg: Cfg, psi) -> np.ndarray:
+    """LUX and the SO sub-step in one Crank-Nicolson solve of every x line."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    a = _arr(cfg, psi)
+    s = 0.5 * cfg.dt if cfg.imag else 0.5j * cfg.dt
+    H = _line_hamiltonian(cfg)
+    I = sp.identity(3 * cfg.nx, dtype=complex, format="csc")
+    lu = spl.splu(sp.csc_matrix(I + s * H))
+    B = sp.csr_matrix(I - s * H)
+    rows = a.reshape(3, -1, cfg.nx)                   # (3, lines, nx)
+    lines = rows.transpose(1, 0, 2).reshape(-1, 3 * cfg.nx)
+    out = lu.solve(np.ascontiguousarray((B @ lines.T)))
+    a[...] = out.T.reshape(-1, 3, cfg.nx).transpose(1, 0, 2).reshape(a.shape)
+    return a
+
+
+def step_unitary_so(cfg: Cfg, psi, nsteps: int = 1) -> np.ndarray:
+    """nsteps steps of the unitary-SO scheme: CALCNU, HERM, the joined
+    LUX + SO solve, LUY (2D), and RENORM in imaginary time."""
+    a = _arr(cfg, psi)
+    for _ in range(int(nsteps)):
+        a = herm(cfg, calcnu(cfg, a))
+        a = cn_x_so(cfg, a)
+        if cfg.dim == 2:
+            a = cn_y(cfg, a)
+        if cfg.imag:
+            a, _ = renorm(cfg, a)
+    return a

@@ -1,0 +1,111 @@
+"""Pins of the oracle's unitary-SO scheme (opt-in, beyond the paper: the SO
+term of Eqs. (p1)-(p2) by Crank-Nicolson together with LUX), each against
+something other than the function itself:
+- at gamma = 0 it is the C oracle's LUX;
+- its line Hamiltonian minus the kinetic part is the C oracle's own H_SO;
+- the solve equals the Cayley transform through an eigendecomposition;
+- real-time lines and whole steps keep the norm exactly for gamma != 0,
+  where the paper's explicit SO sub-step does not;
+- it is the identity for dt -> 0 and consistent to first order with the
+  paper's scheme."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_13507_amd import workloads as W
+
+SO_FORMS = [oracle.SO_PX_SX, oracle.SO_PX_SY, oracle.SO_PX_SZ]
+
+
+def cfg2(nx=20, ny=7, imag=False, so=oracle.SO_PX_SX, gamma=0.6, dt=0.02, **kw):
+    return oracle.Cfg(dim=2, nx=nx, ny=ny, dx=0.3, dy=0.25, imag=imag, so=so, gamma=gamma, dt=dt, **kw)
+
+
+def cfg1(nx=40, imag=False, so=oracle.SO_PX_SX, gamma=0.6, dt=0.02, **kw):
+    return oracle.Cfg(dim=1, nx=nx, ny=1, dx=0.3, dy=0.3, imag=imag, so=so, gamma=gamma, dt=dt, **kw)
+
+
+@pytest.mark.parametrize("imag", [False, True])
+def test_gamma_zero_is_lux(imag):
+    c = cfg2(imag=imag, gamma=0.0)
+    psi = W.random_state((3, c.ny, c.nx), 11)
+    np.testing.assert_allclose(oracle.cn_x_so(c, psi), oracle.cn_x(c, psi), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("so", SO_FORMS)
+def test_line_hamiltonian_so_part_is_the_c_oracles_hso(so):
+    c = cfg1(nx=30, so=so, gamma=0.8)
+    c0 = cfg1(nx=30, so=so, gamma=0.0)
+    psi = W.random_state((3, c.nx), 12)
+    v = psi.reshape(-1)
+    so_part = (oracle._line_hamiltonian(c) - oracle._line_hamiltonian(c0)) @ v
+    np.testing.assert_allclose(so_part.reshape(3, c.nx), oracle.apply_hso(c, psi), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("imag", [False, True])
+@pytest.mark.parametrize("so", SO_FORMS)
+def test_solve_is_the_cayley_transform(imag, so):
+    c = cfg1(nx=24, imag=imag, so=so, gamma=0.9, dt=0.05)
+    psi = W.random_state((3, c.nx), 13)
+    H = oracle._line_hamiltonian(c).toarray()
+    mu, V = np.linalg.eigh(H)
+    s = 0.5 * c.dt if imag else 0.5j * c.dt
+    want = V @ (((1 - s * mu) / (1 + s * mu)) * (V.conj().T @ psi.reshape(-1)))
+    np.testing.assert_allclose(oracle.cn_x_so(c, psi).reshape(-1), want, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("so", SO_FORMS)
+def test_real_time_lines_are_unitary(so):
+    c = cfg2(so=so, gamma=1.3, dt=0.05)
+    psi = W.random_state((3, c.ny, c.nx), 14)
+    out = oracle.cn_x_so(c, psi)
+    assert abs(np.linalg.norm(out) / np.linalg.norm(psi) - 1) < 1e-14
+
+
+def test_real_time_steps_keep_the_norm_where_the_paper_scheme_does_not():
+    nx, ny, dx = 32, 24, 0.3
+    prm = dict(c0=2.0, c2=-0.4, gamma=0.8, omega=0.3, dt=0.01, so=oracle.SO_PX_SX)
+    c = oracle.Cfg(dim=2, nx=nx, ny=ny, dx=dx, dy=dx, imag=False, **prm)
+    base = W.gaussian(2, nx, ny, dx, dx, phases=(0.3, 1.1, 2.0), width=1.5)
+    psi0 = base * (1 + W.random_state(base.shape, 15, 0.05))
+    n0 = np.linalg.norm(psi0)
+    uso = oracle.step_unitary_so(c, psi0, 40)
+    paper = oracle.step(c, psi0, 40)
+    assert abs(np.linalg.norm(uso) / n0 - 1) < 1e-13
+    assert np.linalg.norm(paper) / n0 - 1 > 1e-7
+
+
+def test_first_order_consistent_with_the_paper_scheme():
+    """One step of either scheme differs by O(dt^2): halving dt quarters it."""
+    nx, ny, dx = 32, 20, 0.3
+    base = W.gaussian(2, nx, ny, dx, dx, phases=(0.3, 1.1, 2.0), width=1.5)
+    psi0 = base * (1 + W.random_state(base.shape, 16, 0.05))
+    diffs = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        c = oracle.Cfg(dim=2, nx=nx, ny=ny, dx=dx, dy=dx, imag=False, c0=2.0, c2=-0.4, gamma=0.8,
+                       omega=0.3, dt=dt, so=oracle.SO_PX_SX)
+        diffs.append(np.linalg.norm(oracle.step_unitary_so(c, psi0, 1) - oracle.step(c, psi0, 1)))
+    r1, r2 = diffs[0] / diffs[1], diffs[1] / diffs[2]
+    assert 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4, diffs
+
+
+def test_imaginary_time_relaxes_to_the_same_ground_state_energy():
+    """Both schemes are Lie splittings of the same Hamiltonian: their
+    imaginary-time fixed points agree to O(dt) and converge together."""
+    nx, ny, dx = 40, 40, 0.4
+    base = W.gaussian(2, nx, ny, dx, dx, width=2.0)
+    es = {}
+    for dt in (4e-3, 2e-3):
+        c = oracle.Cfg(dim=2, nx=nx, ny=ny, dx=dx, dy=dx, imag=True, c0=5.0, c2=-0.5, gamma=0.5,
+                       omega=0.1, dt=dt, so=oracle.SO_PX_SX)
+        eu = oracle.observables(c, oracle.step_unitary_so(c, base, int(8 / dt)))["E"]
+        ep = oracle.observables(c, oracle.step(c, base, int(8 / dt)))["E"]
+        es[dt] = abs(eu - ep)
+    assert es[4e-3] < 2e-3
+    assert es[2e-3] < 0.6 * es[4e-3]
+
+
+def test_rejects_forms_with_y_derivatives():
+    c = cfg2(so=oracle.SO_RASHBA)
+    with pytest.raises(ValueError):
+        oracle.cn_x_so(c, W.random_state((3, c.ny, c.nx), 17))
