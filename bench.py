@@ -15,6 +15,9 @@ Prints one JSON line:
              the 8 TB/s HBM peak;
   cpu_baseline  the CPU oracle on the host cores, on a bounded sample of the
              same workload (first steps from the same initial state).
+Beside them: the forward+adjoint cost ratio, the batched-vs-serial
+comparison, the imaginary-time workloads, and the same 1024^2 workload under
+the opt-in unitary-SO scheme (unitary_so).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -143,6 +146,43 @@ def imag_workloads():
     return out
 
 
+def unitary_so(steps: int = 1000, warmup: int = 50, every: int = 7):
+    """The opt-in unitary-SO scheme on the 1024^2 real-time workload: step
+    rate, x-pass and y-pass kernel times (HIP events on every `every`-th
+    step), the x-pass rate on its algorithmic bytes, and the norm change over
+    the run (exact to rounding under this scheme)."""
+    import torch
+
+    from paper_2009_13507_amd import api
+    from paper_2009_13507_amd import workloads as W
+
+    w = W.W2D_REAL
+    psi0 = W.initial_2d_real(w)
+    state = torch.from_numpy(psi0).to("cuda:0")
+    g = api.Grid(state, w.dx, w.dy)
+    g.set_params(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, dt=w.dt, so=w.so)
+    g.set_scheme(api.SCHEME_UNITARY_SO)
+    g.step_real(warmup)
+    n0 = g.observables()["N"]
+    g.profile(every, capacity=steps // every + 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step_real(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = g.profile_read()
+    g.profile(0)
+    n1 = g.observables()["N"]
+    g.close()
+    npts = w.nx * w.ny
+    per_launch = BYTES_PER_PT_PASS["f64"] * npts
+    return {"workload": w.name + " (unitary-SO scheme)", "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "pt_steps_per_s": npts * steps / el,
+            "kernels_ms": {"xpass": prof["x_ms"], "ypass": prof["y_ms"], "profiled_steps": prof["steps"]},
+            "xpass_achieved_GBs": per_launch / (prof["x_ms"] * 1e-3) / 1e9,
+            "norm_change": n1 - n0}
+
+
 def batch_compare(steps: int = 200, warmup: int = 20):
     """The 64-instance imaginary-time batch (sizes 128..512, seed-1 draw):
     batched (autotuned launch shape, graph replay) against one grid at a
@@ -208,6 +248,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint cost ratio")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-serial comparison")
+    ap.add_argument("--no-uso", action="store_true", help="skip the unitary-SO scheme figures")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run torch copies of the state size (counter calibration)")
     args = ap.parse_args()
@@ -299,6 +340,8 @@ def main():
     }
     if not args.no_adjoint and args.dtype == "f64":
         line["adjoint_cost_ratio"] = adjoint_ratio()
+    if not args.no_uso and args.dtype == "f64":
+        line["unitary_so"] = unitary_so()
     if not args.no_batch:
         line["batch_c4"] = batch_compare()
         line["imag_workloads"] = imag_workloads()

@@ -75,6 +75,12 @@ enum ssgp_so {
  * N_{-1} is zero, or a radicand is negative. */
 enum ssgp_renorm { SSGP_RENORM_AUTO = 0, SSGP_RENORM_NORM = 1, SSGP_RENORM_FIXED_M = 2 };
 
+/* Time-stepping scheme (ssgp_set_scheme).  PAPER: the splitting of Sec. 2 and
+ * App. A, with the explicit SO sub-step of Eqs. (p1)-(p2).  UNITARY_SO (opt-in,
+ * beyond the paper): the SO term is taken by Crank-Nicolson together with the
+ * x kinetic term. */
+enum ssgp_scheme { SSGP_SCHEME_PAPER = 0, SSGP_SCHEME_UNITARY_SO = 1 };
+
 typedef struct {
     double c0, c2;     /* density couplings of Eqs. (1)-(2)                 */
     double gamma;      /* spin-orbit strength                              */
@@ -114,6 +120,21 @@ int ssgp_set_state(ssgp_grid g, void *psi_dev);
  * unknown so/renorm value, a y-dependent SO form on a 1D grid, a 1D-only SO
  * form (p_x Sigma_y, p_x Sigma_z) on a 2D grid, or |mag0| > 1. */
 int ssgp_set_params(ssgp_grid g, const ssgp_params *p);
+
+/* Selects the time-stepping scheme (default SSGP_SCHEME_PAPER).
+ * SSGP_SCHEME_UNITARY_SO, for 2D grids with gamma p_x Sigma_x (or no SO):
+ * each step is CALCNU, HERM, then one Crank-Nicolson solve of every row with
+ * H_x = T (x) I + gamma (-i d_x) (x) S_x (the SO sub-step of Eqs. (p1)-(p2)
+ * and LUX of Table 1 joined, S_x the spin-1 matrix of Eq. (3), central
+ * differences, zero ghosts), then LUY and, in imaginary time, RENORM.  In
+ * real time the step then conserves the norm exactly for gamma != 0.  The
+ * library solves each row in the eigenbasis of S_x.  EINVAL for an unknown
+ * scheme, a 1D grid, or parameters with another SO form (ssgp_set_params
+ * then refuses those too); a step call returns EINVAL when the symmetrised
+ * line matrix is not diagonally dominant (real time: dt gamma >= 2 dx).
+ * The adjoint entry points (ssgp_step_real_seq, ssgp_step_real_adjoint)
+ * return ESTATE under this scheme.  Drops the captured step graphs. */
+int ssgp_set_scheme(ssgp_grid g, int scheme);
 
 /* Piecewise-constant Rabi control for real-time steps: the step with index
  * n (see ssgp_set_step_index) uses omega[n / steps_per_seg] (clamped to the

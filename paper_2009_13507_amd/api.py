@@ -16,6 +16,9 @@ from ._lib import Obs, Params, SSGPError, check
 
 SO_NONE, SO_PX_SX, SO_PX_SY, SO_PX_SZ, SO_RASHBA, SO_DRESSELHAUS, SO_ERD = range(7)
 RENORM_AUTO, RENORM_NORM, RENORM_FIXED_M = range(3)
+# PAPER: the paper's splitting; UNITARY_SO (opt-in): the SO term by
+# Crank-Nicolson together with the x kinetic term (2D, gamma p_x Sigma_x)
+SCHEME_PAPER, SCHEME_UNITARY_SO = range(2)
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -94,6 +97,9 @@ class Grid:
         p = p if p is not None else params(**kw)
         check(self._lib.ssgp_set_params(self._h, ctypes.byref(p)))
         self.p = p
+
+    def set_scheme(self, scheme: int):
+        check(self._lib.ssgp_set_scheme(self._h, int(scheme)))
 
     def set_omega_schedule(self, omega, steps_per_seg: int):
         arr = (ctypes.c_double * len(omega))(*[float(v) for v in omega])

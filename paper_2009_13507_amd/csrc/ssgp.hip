@@ -89,9 +89,11 @@ struct CNHost {
     int levels;      // scan levels needed for carries above 2^-64
 };
 
-static CNHost cn_tables(int n, double h, cd s, int L, int nchunks, int max_levels) {
+// Tables of the symmetric Toeplitz matrix tridiag(o, d, o), with rdiag the
+// diagonal of the right-hand-side matrix divided by o (its off-diagonal
+// divided by o is -1).
+static CNHost cn_tables_do(int n, cd d, cd o, cd rdiag, int L, int nchunks, int max_levels) {
     CNHost t;
-    const cd d = 1.0 + s / (h * h), o = -s / (2.0 * h * h);
     t.cp.resize(n);
     t.cp[0] = o / d;
     for (int i = 1; i < n; ++i) t.cp[i] = o / (d - o * t.cp[i - 1]);
@@ -101,7 +103,7 @@ static CNHost cn_tables(int n, double h, cd s, int L, int nchunks, int max_level
         for (int i = k * L; i < std::min(n, (k + 1) * L); ++i) t.chunkA[k] *= -t.cp[i];
         if (k * L < n) amax = std::max(amax, std::abs(t.chunkA[k]));
     }
-    t.rdiag = (1.0 - s / (h * h)) / o;
+    t.rdiag = rdiag;
     // A carry from W+1 or more chunks back is scaled by at most amax^(W+1);
     // take the smallest W = 2^levels - 1 with amax^(W+1) <= 2^-64.
     int levels = max_levels;
@@ -112,6 +114,11 @@ static CNHost cn_tables(int n, double h, cd s, int L, int nchunks, int max_level
     }
     t.levels = levels;
     return t;
+}
+
+static CNHost cn_tables(int n, double h, cd s, int L, int nchunks, int max_levels) {
+    const cd d = 1.0 + s / (h * h), o = -s / (2.0 * h * h);
+    return cn_tables_do(n, d, o, (1.0 - s / (h * h)) / o, L, nchunks, max_levels);
 }
 
 template <typename R> struct CNDev {
@@ -305,6 +312,8 @@ struct GridCore {
     };
     std::vector<StepGraph> graphs;
     hipStream_t cap = nullptr;
+    int scheme = SSGP_SCHEME_PAPER;
+    cd uso_rot[9];  // unitary-SO scheme: eigenvectors of the SO spin matrix (columns)
     void clear_graphs() {
         if (graphs.empty()) return;
         (void)hipStreamSynchronize(stream);  // no replay of them still in flight
@@ -322,6 +331,8 @@ template <typename R> struct Tables {
     CNDev<R> x[NMODES];   // x lines as 64 chunks (1D, adjoint and batched rows)
     CNDev<R> xb[NMODES];  // x lines as 256 chunks (2D x-pass)
     CNDev<R> y[NMODES];
+    CNDev<R> xu[NMODES][3];  // unitary-SO scheme: the three symmetrised lines
+    DevBuf ramp[NMODES];     //   and their phase ramps [3][nx]
 };
 
 struct ssgp_grid_s : GridCore {
@@ -345,6 +356,69 @@ template <typename R> static Tables<R> &tables(ssgp_grid g);
 template <> Tables<double> &tables<double>(ssgp_grid g) { return g->t64; }
 template <> Tables<float> &tables<float>(ssgp_grid g) { return g->t32; }
 
+// ------------------------------------------------- unitary-SO scheme --
+// gamma p_x S_x is solved together with CN_x: the line operator is
+// H = T (x) I + (-i d_x) (x) gamma S_x.  With S_x = W diag(1, 0, -1) W^H,
+// component c of W^H psi is the scalar line problem (I + sH_c) psi' =
+// (I - sH_c) psi, H_c = T + gamma lambda_c (-i d_x): tridiagonal Toeplitz
+// with diagonal d = 1 + s/h^2, upper u = s(-1/(2h^2) - i gamma lambda_c/(2h))
+// and lower l = s(-1/(2h^2) + i gamma lambda_c/(2h)).  For s = i dt/2 and for
+// s = dt/2, |u| = |l|, so rho = sqrt(l/u) has modulus 1, and with
+// D = diag(rho^i), D^-1 (I + sH_c) D = tridiag(o, d, o) with o = u rho (and
+// the right-hand-side matrix 2I - (I + sH_c) transforms alike).  The line is
+// solved as CN_x is, on conj(rho^i) (W^H psi)_c, and multiplied back by rho^i.
+static void sx_eigen(cd W[9], double lam[3]) {
+    const double r = 1.0 / std::sqrt(2.0);
+    const cd w[9] = {0.5, r, 0.5, r, 0.0, -r, 0.5, -r, 0.5};  // W[j][c], row-major
+    for (int q = 0; q < 9; ++q) W[q] = w[q];
+    lam[0] = 1.0;
+    lam[1] = 0.0;
+    lam[2] = -1.0;
+}
+
+template <typename R> static int build_uso(ssgp_grid g, int mode, int km) {
+    Tables<R> &T = tables<R>(g);
+    cd W[9], Sx[9], Sy[9], Sz[9];
+    double lam[3];
+    sx_eigen(W, lam);
+    spin_matrices(Sx, Sy, Sz);
+    for (int j = 0; j < 3; ++j)  // W diag(lam) W^H must give S_x back
+        for (int k = 0; k < 3; ++k) {
+            cd m = 0.0;
+            for (int c = 0; c < 3; ++c) m += W[3 * j + c] * lam[c] * std::conj(W[3 * k + c]);
+            if (std::abs(m - Sx[3 * j + k]) > 1e-15) return fail(SSGP_EDEVICE, "S_x eigenvectors inconsistent");
+        }
+    for (int q = 0; q < 9; ++q) g->uso_rot[q] = W[q];
+    const double h = g->dx, gam = g->p.so == SSGP_SO_PX_SX ? g->p.gamma : 0.0;
+    const cd s = cn_s(mode, g->p.dt), I(0.0, 1.0);
+    const cd d = 1.0 + s / (h * h);
+    CNHost tab[3];
+    std::vector<cx<R>> ramp((size_t)3 * g->nx);
+    int levels = 1;
+    for (int c = 0; c < 3; ++c) {
+        const cd u = s * (-0.5 / (h * h) - I * gam * lam[c] / (2.0 * h));
+        const cd l = s * (-0.5 / (h * h) + I * gam * lam[c] / (2.0 * h));
+        cd rho = std::sqrt(l / u);
+        rho /= std::abs(rho);
+        const cd o = u * rho;
+        if (!(std::abs(d) > 2.0 * std::abs(o)))
+            return fail(SSGP_EINVAL, "unitary SO: the line matrix is not diagonally dominant (dt gamma too large)");
+        tab[c] = cn_tables_do(g->nx, d, o, (2.0 - d) / o, km, XPASS_THREADS, 6);
+        levels = std::max(levels, tab[c].levels);
+        const double th = std::arg(rho);
+        for (int i = 0; i < g->nx; ++i)
+            ramp[(size_t)c * g->nx + i] = tor<R>(cd(std::cos(th * i), std::sin(th * i)));
+    }
+    for (int c = 0; c < 3; ++c) {
+        tab[c].levels = levels;
+        SSGP_TRY(upload_cn<R>(T.xu[mode][c], tab[c], g->nx, km, XPASS_THREADS, g->stream));
+    }
+    SSGP_TRY(T.ramp[mode].ensure(ramp.size() * sizeof(cx<R>)));
+    HIP_TRY(hipMemcpyAsync(T.ramp[mode].p, ramp.data(), ramp.size() * sizeof(cx<R>), hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return SSGP_OK;
+}
+
 template <typename R> static int build_tables(ssgp_grid g, int mode) {
     if (g->built_mode_mask & (1 << mode)) return SSGP_OK;
     g->clear_graphs();  // the graphs hold pointers into the tables
@@ -361,6 +435,7 @@ template <typename R> static int build_tables(ssgp_grid g, int mode) {
         while ((YTX << maxlv) < 64) ++maxlv;
         SSGP_TRY(upload_cn<R>(T.y[mode], cn_tables(g->ny, g->dy, s, ys.L, ys.P, maxlv), g->ny, ys.L, ys.P,
                               g->stream));
+        if (g->scheme == SSGP_SCHEME_UNITARY_SO && mode != MODE_ADJ) SSGP_TRY(build_uso<R>(g, mode, km));
     }
     g->built_mode_mask |= 1 << mode;
     return SSGP_OK;
@@ -451,6 +526,16 @@ static XArgs<R> x_args(ssgp_grid g, int mode, const void *src, void *dst, double
     a.rdiag = T.x[mode].rdiag;
     fill_so(a, *g, mode);
     a.so_y = 0;
+    a.ramp = nullptr;
+    if (g->scheme == SSGP_SCHEME_UNITARY_SO && g->dim == 2 && mode != MODE_ADJ) {
+        a.ramp = T.ramp[mode].template as<cx<R>>();
+        for (int q = 0; q < 9; ++q) a.rot[q] = tor<R>(g->uso_rot[q]);
+        for (int c = 0; c < 3; ++c) {
+            a.cu[c] = T.xu[mode][c].coef();
+            a.rdiag_u[c] = T.xu[mode][c].rdiag;
+        }
+        a.qxmask = 0;  // the SO term is in the line solve
+    }
     return a;
 }
 
@@ -705,6 +790,8 @@ static int check_params(const GridCore &g, const ssgp_params *p) {
     if (g.dim == 2 && (p->so == SSGP_SO_PX_SY || p->so == SSGP_SO_PX_SZ))
         return fail(SSGP_EINVAL, "SO form %d is defined for 1D grids", p->so);
     if (std::fabs(p->mag0) > 1.0) return fail(SSGP_EINVAL, "|mag0| must be <= 1");
+    if (g.scheme == SSGP_SCHEME_UNITARY_SO && p->so != SSGP_SO_NONE && p->so != SSGP_SO_PX_SX)
+        return fail(SSGP_EINVAL, "the unitary-SO scheme takes gamma p_x Sigma_x (or no SO)");
     return SSGP_OK;
 }
 
@@ -773,6 +860,23 @@ extern "C" int ssgp_set_params(ssgp_grid g, const ssgp_params *p) {
     return SSGP_OK;
 }
 
+extern "C" int ssgp_set_scheme(ssgp_grid g, int scheme) {
+    if (!g) return fail(SSGP_EINVAL, "grid is NULL");
+    if (scheme != SSGP_SCHEME_PAPER && scheme != SSGP_SCHEME_UNITARY_SO)
+        return fail(SSGP_EINVAL, "unknown scheme %d", scheme);
+    if (scheme == SSGP_SCHEME_UNITARY_SO) {
+        if (g->dim != 2) return fail(SSGP_EINVAL, "the unitary-SO scheme is for 2D grids");
+        if (g->have_params && g->p.so != SSGP_SO_NONE && g->p.so != SSGP_SO_PX_SX)
+            return fail(SSGP_EINVAL, "the unitary-SO scheme takes gamma p_x Sigma_x (or no SO)");
+    }
+    if (scheme != g->scheme) {
+        g->clear_graphs();
+        g->built_mode_mask = 0;
+        g->scheme = scheme;
+    }
+    return SSGP_OK;
+}
+
 extern "C" int ssgp_set_omega_schedule(ssgp_grid g, const double *omega, int nseg, int steps_per_seg) {
     if (!g) return fail(SSGP_EINVAL, "grid is NULL");
     if (nseg < 0 || (nseg > 0 && (!omega || steps_per_seg < 1))) return fail(SSGP_EINVAL, "bad schedule");
@@ -813,6 +917,7 @@ extern "C" int ssgp_step_real(ssgp_grid g, int nsteps) {
 extern "C" int ssgp_step_real_seq(ssgp_grid g, const void *src, void *dst, int nsteps) {
     if (!g || !src || !dst) return fail(SSGP_EINVAL, "NULL argument");
     if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
+    if (g->scheme != SSGP_SCHEME_PAPER) return fail(SSGP_ESTATE, "the adjoint path follows the paper's scheme");
     if (nsteps < 0) return fail(SSGP_EINVAL, "nsteps < 0");
     return g->dtype == SSGP_C128 ? step_real_t<double>(g, src, dst, nsteps, true)
                                  : step_real_t<float>(g, src, dst, nsteps, true);
@@ -871,6 +976,7 @@ extern "C" int ssgp_observables(ssgp_grid g, ssgp_obs *out) {
 extern "C" int ssgp_step_real_adjoint(ssgp_grid g, const void *states_dev, void *lambda_dev, int nsteps) {
     if (!g || !states_dev || !lambda_dev) return fail(SSGP_EINVAL, "NULL argument");
     if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
+    if (g->scheme != SSGP_SCHEME_PAPER) return fail(SSGP_ESTATE, "the adjoint path follows the paper's scheme");
     if (nsteps < 0) return fail(SSGP_EINVAL, "nsteps < 0");
     return g->dtype == SSGP_C128 ? adjoint_steps<double>(g, states_dev, lambda_dev, nsteps)
                                  : adjoint_steps<float>(g, states_dev, lambda_dev, nsteps);

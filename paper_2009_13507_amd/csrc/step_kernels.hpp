@@ -528,6 +528,16 @@ template <typename R> struct XArgs {
     int so_y;                  // 1: add qy terms with rows iy +- 1 of src
     cx<R> qy[9];
     unsigned qymask;
+    // Unitary-SO scheme (x-derivative SO forms; no qx terms then): the SO
+    // term is solved together with CN_x.  In the eigenbasis of the SO spin
+    // matrix (columns of rot, row-major rot[3 j + c]) component c is a
+    // tridiagonal Toeplitz system with off-diagonals of equal modulus; the
+    // diagonal similarity by the unit phases ramp[c][i] makes it symmetric,
+    // and it is solved like CN_x with its own tables cu[c] and rdiag_u[c].
+    const cx<R> *ramp;         // [3][nx], or nullptr: the paper's scheme
+    cx<R> rot[9];
+    LineCoef<R> cu[3];
+    cx<R> rdiag_u[3];
 };
 
 constexpr int XPASS_THREADS = 256;
@@ -695,7 +705,7 @@ __device__ __forceinline__ void store_row(cx<R> *dst, long long plane, int nx, c
 
 // Everything after the loads, for one row whose KM points per thread are in
 // v (zero beyond nx).
-template <typename R, int KM, int CM, bool FULL, bool SOY>
+template <typename R, int KM, int CM, bool FULL, bool SOY, bool USO>
 __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)[3][KM], XShared<R, KM> &sh) {
     cx<R> *E = sh.E;
     auto &scA = sh.scA;
@@ -754,6 +764,21 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
                     const R xv = a.x0 + R(i) * a.dx;
                     pointwise(v[0][k], v[1][k], v[2][k], R(0.5) * xv * xv + vy, a.m);
                 }
+            }
+        }
+    }
+    if constexpr (USO) {
+        // into the symmetrised eigenbasis: conj(ramp) * (rot^H v)
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = i0 + k;
+            if (FULL || i < nx) {
+                cx<R> w[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    w[c] = conj(a.rot[c]) * v[0][k] + conj(a.rot[3 + c]) * v[1][k] + conj(a.rot[6 + c]) * v[2][k];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c][k] = conj(a.ramp[c * nx + i]) * w[c];
             }
         }
     }
@@ -839,21 +864,25 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         for (int k = 0; k < KM; ++k) {
             const cx<R> pu = k > 0 ? u[j][k > 0 ? k - 1 : 0] : ub;
             const cx<R> nu = k + 1 < KM ? u[j][k + 1 < KM ? k + 1 : 0] : ua;
-            r[j][k] = (FULL || i0 + k < nx) ? cn_rhs(a.rdiag, u[j][k], pu + nu) : czero<R>();
+            r[j][k] = (FULL || i0 + k < nx) ? cn_rhs(USO ? a.rdiag_u[j] : a.rdiag, u[j][k], pu + nu) : czero<R>();
         }
     }
 
     // ---- Crank-Nicolson solve of the three lines, chunk = this thread's points
     const int len = FULL ? KM : max(0, min(KM, nx - i0));
-    const ChunkCoef<R, KM, CM> cpl(a.cx_, i0);
+    // one coefficient set for the three lines, or (USO) one per line
+    const ChunkCoef<R, KM, CM> cpl(USO ? a.cu[0] : a.cx_, i0);
+    const ChunkCoef<R, KM, CM> cpl1(USO ? a.cu[1] : a.cx_, i0);
+    const ChunkCoef<R, KM, CM> cpl2(USO ? a.cu[2] : a.cx_, i0);
+    auto coef = [&](int j) -> const ChunkCoef<R, KM, CM> & { return j == 0 ? cpl : j == 1 ? cpl1 : cpl2; };
     const cx<R> Ak = a.cx_.chunkA[tid];
-    const int levels = a.cx_.levels;
+    const int levels = USO ? a.cu[0].levels : a.cx_.levels;  // (USO: the host gives the three the same)
     cx<R> A[3], B[3];
     // forward sweep: chunk eliminations, scan, carries across wavefronts
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        A[j] = Ak;
-        B[j] = fwd_local<R, KM>(r[j], len, cpl);
+        A[j] = USO ? a.cu[j].chunkA[tid] : Ak;
+        B[j] = fwd_local<R, KM>(r[j], len, USO ? coef(j) : cpl);
     }
     wave_scan_up3<R>(A, B, levels);
     if (lane == 63) {
@@ -882,12 +911,17 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         const cx<R> prev = shfl_up(cfma(A[j], carry[j], B[j]), 1);
         if (lane >= 1) carry[j] = prev;
     }
-    fwd_fix3<R, KM>(r, len, cpl, carry);
+    if constexpr (USO) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) fwd_fix<R, KM>(r[j], len, coef(j), carry[j]);
+    } else {
+        fwd_fix3<R, KM>(r, len, cpl, carry);
+    }
     // back substitution: chunk sweeps, reverse scan, carries
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        A[j] = Ak;
-        B[j] = bwd_local<R, KM>(r[j], len, cpl);
+        A[j] = USO ? a.cu[j].chunkA[tid] : Ak;
+        B[j] = bwd_local<R, KM>(r[j], len, USO ? coef(j) : cpl);
     }
     wave_scan_down3<R>(A, B, levels);
     if (lane == 0) {
@@ -916,12 +950,32 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         const cx<R> next = shfl_down(cfma(A[j], carry[j], B[j]), 1);
         if (lane < 63) carry[j] = next;
     }
-    bwd_fix3<R, KM>(r, len, cpl, carry);
+    if constexpr (USO) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) bwd_fix<R, KM>(r[j], len, coef(j), carry[j]);
+        // back from the symmetrised eigenbasis: rot (ramp * r)
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = i0 + k;
+            if (FULL || i < nx) {
+                cx<R> w[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) w[c] = a.ramp[c * nx + i] * r[c][k];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) r[j][k] = a.rot[3 * j] * w[0] + a.rot[3 * j + 1] * w[1] + a.rot[3 * j + 2] * w[2];
+            }
+        }
+    } else {
+        bwd_fix3<R, KM>(r, len, cpl, carry);
+    }
     store_row<R, KM, FULL>(dst, a.plane, nx, r, sh.xch[w]);
 }
 
-template <typename R, int KM, int CM, bool FULL, bool SOY>
-__global__ void __launch_bounds__(XPASS_THREADS) __attribute__((amdgpu_waves_per_eu(KM <= 4 ? 4 : 1))) xpass_kernel(XArgs<R> a) {
+// (The unitary-SO form holds three coefficient sets per thread: from 2 points
+// per thread on it takes the registers of 2 wavefronts per SIMD.)
+template <typename R, int KM, int CM, bool FULL, bool SOY, bool USO = false>
+__global__ void __launch_bounds__(XPASS_THREADS)
+__attribute__((amdgpu_waves_per_eu(USO ? (KM <= 1 ? 4 : 2) : (KM <= 4 ? 4 : 1)))) xpass_kernel(XArgs<R> a) {
     __shared__ XShared<R, KM> sh;
     const int nx = FULL ? XPASS_THREADS * KM : a.nx;
     const int row = blockIdx.x;
@@ -934,7 +988,7 @@ __global__ void __launch_bounds__(XPASS_THREADS) __attribute__((amdgpu_waves_per
 #pragma unroll
         for (int j = 0; j < 3; ++j) v[j][k] = (FULL || i < nx) ? src[j * a.plane + i] : czero<R>();
     }
-    xpass_row<R, KM, CM, FULL, SOY>(a, row, v, sh);
+    xpass_row<R, KM, CM, FULL, SOY, USO>(a, row, v, sh);
 }
 
 // ------------------------------------------------------------- y-pass ---

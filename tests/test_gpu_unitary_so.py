@@ -1,0 +1,166 @@
+"""The opt-in unitary-SO scheme on the GPU (the SO term by Crank-Nicolson
+together with LUX, solved per row in the eigenbasis of S_x) against the
+oracle's definition of it: relative L2 <= 1e-10 in FP64 and <= 1e-5 in FP32
+over every x-pass shape (1, 2, 4 and 8 points per thread, full and ragged
+rows), in real and imaginary time; exact real-time norm; graph replays
+bitwise equal to one-by-one launches; and the refusals."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2009_13507_amd import api  # noqa: E402
+from paper_2009_13507_amd import workloads as W  # noqa: E402
+from paper_2009_13507_amd._lib import SSGPError  # noqa: E402
+
+DEV = "cuda:0"
+PRM = dict(c0=2.0, c2=-0.3, gamma=0.7, omega=0.15, so=api.SO_PX_SX)
+SHAPES = [(72, 40), (256, 20), (300, 9), (512, 9), (700, 6), (1024, 5), (1500, 3), (2048, 3)]
+
+
+def start(nx, ny, dx, seed):
+    base = W.gaussian(2, nx, ny, dx, dx, phases=(0.3, 1.1, 2.0), width=0.18 * min(nx, 4 * ny) * dx)
+    return base * (1 + W.random_state(base.shape, seed, 0.05))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run(psi0, dx, imag, dt, calls, dtype=torch.complex128, **prm):
+    t = torch.from_numpy(psi0.copy()).to(DEV, dtype)
+    g = api.Grid(t, dx, dx)
+    g.set_params(dt=dt, **prm)
+    g.set_scheme(api.SCHEME_UNITARY_SO)
+    for n in calls:
+        (g.step_imag if imag else g.step_real)(n)
+    torch.cuda.synchronize()
+    out = t.cpu().numpy().astype(np.complex128)
+    g.close()
+    return out
+
+
+@pytest.mark.parametrize("imag", [False, True], ids=["real", "imag"])
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_unitary_so_matches_oracle(nx, ny, imag):
+    dx, dt = 0.1, 2e-3
+    psi0 = start(nx, ny, dx, nx + ny)
+    print(f"unitary SO nx={nx} ny={ny} imag={imag}", flush=True)
+    got = run(psi0, dx, imag, dt, (3, 1, 4), **PRM)
+    cfg = oracle.Cfg(dim=2, nx=nx, ny=ny, dx=dx, dy=dx, imag=imag, dt=dt, **PRM)
+    want = oracle.step_unitary_so(cfg, psi0, 8)
+    assert rel(got, want) < 1e-10
+
+
+@pytest.mark.parametrize("nx,ny", [(128, 96), (700, 6), (1024, 5)])
+def test_unitary_so_complex64(nx, ny):
+    dx, dt = 0.1, 2e-3
+    psi0 = start(nx, ny, dx, 7)
+    got = run(psi0, dx, False, dt, (6,), dtype=torch.complex64, **PRM)
+    cfg = oracle.Cfg(dim=2, nx=nx, ny=ny, dx=dx, dy=dx, imag=False, dt=dt, **PRM)
+    want = oracle.step_unitary_so(cfg, psi0, 6)
+    assert rel(got, want) < 1e-5
+
+
+def test_unitary_so_keeps_the_real_time_norm():
+    n, dx = 256, 0.1
+    psi0 = W.gaussian(2, n, n, dx, dx, phases=(0.3, 1.1, 2.0), width=2.0)
+    t = torch.from_numpy(psi0.copy()).to(DEV)
+    g = api.Grid(t, dx, dx)
+    g.set_params(c0=2.0, c2=0.1, gamma=0.8, omega=0.2, dt=5e-3, so=api.SO_PX_SX)
+    g.set_scheme(api.SCHEME_UNITARY_SO)
+    n0 = g.observables()["N"]
+    g.step_real(400)
+    o = g.observables()
+    g.close()
+    assert abs(o["N"] - n0) < 1e-12
+    # the paper's scheme with the explicit SO sub-step grows the norm
+    t = torch.from_numpy(psi0.copy()).to(DEV)
+    g = api.Grid(t, dx, dx)
+    g.set_params(c0=2.0, c2=0.1, gamma=0.8, omega=0.2, dt=5e-3, so=api.SO_PX_SX)
+    g.step_real(400)
+    grow = g.observables()["N"] - n0
+    g.close()
+    assert grow > 1e-6
+
+
+def test_unitary_so_graph_replays_match_one_by_one_launches():
+    nx, ny, dx = 96, 64, 0.1
+    psi0 = start(nx, ny, dx, 3)
+    outs = []
+    for eager in (True, False):
+        t = torch.from_numpy(psi0.copy()).to(DEV)
+        g = api.Grid(t, dx, dx)
+        g.set_params(dt=2e-3, **PRM)
+        g.set_scheme(api.SCHEME_UNITARY_SO)
+        if eager:
+            g.profile(1, 100000)
+        for n in (13, 64, 7):
+            g.step_real(n)
+            _ = (t.abs() ** 2).sum().item()
+        torch.cuda.synchronize()
+        outs.append(t.cpu().numpy())
+        g.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_switching_schemes():
+    """Back on the paper's scheme the grid steps as before (oracle.step)."""
+    nx, ny, dx, dt = 80, 24, 0.1, 2e-3
+    psi0 = start(nx, ny, dx, 5)
+    t = torch.from_numpy(psi0.copy()).to(DEV)
+    g = api.Grid(t, dx, dx)
+    g.set_params(dt=dt, **PRM)
+    g.set_scheme(api.SCHEME_UNITARY_SO)
+    g.step_real(3)
+    g.set_scheme(api.SCHEME_PAPER)
+    g.step_real(4)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    g.close()
+    cfg = oracle.Cfg(dim=2, nx=nx, ny=ny, dx=dx, dy=dx, imag=False, dt=dt, **PRM)
+    want = oracle.step(cfg, oracle.step_unitary_so(cfg, psi0, 3), 4)
+    assert rel(got, want) < 1e-10
+
+
+def test_unitary_so_refusals():
+    t1 = torch.from_numpy(W.gaussian(1, 64, 1, 0.1, 0.1)).to(DEV)
+    g1 = api.Grid(t1, 0.1)
+    with pytest.raises(SSGPError):
+        g1.set_scheme(api.SCHEME_UNITARY_SO)          # 1D grid
+    g1.close()
+    nx, ny, dx = 64, 48, 0.1
+    t = torch.from_numpy(start(nx, ny, dx, 9)).to(DEV)
+    g = api.Grid(t, dx, dx)
+    with pytest.raises(SSGPError):
+        g.set_scheme(7)                                # unknown scheme
+    g.set_params(c0=1.0, gamma=0.5, dt=1e-3, so=api.SO_RASHBA)
+    with pytest.raises(SSGPError):
+        g.set_scheme(api.SCHEME_UNITARY_SO)           # y-derivative SO form
+    g.set_params(c0=1.0, gamma=0.5, dt=1e-3, so=api.SO_PX_SX)
+    g.set_scheme(api.SCHEME_UNITARY_SO)
+    with pytest.raises(SSGPError):
+        g.set_params(c0=1.0, gamma=0.5, dt=1e-3, so=api.SO_ERD)
+    with pytest.raises(SSGPError):
+        g.step_real_seq(t, torch.empty((1,) + tuple(t.shape), dtype=t.dtype, device=DEV), 1)
+    # dt gamma >= 2 dx: the symmetrised line matrix is not diagonally dominant
+    g.set_params(c0=1.0, gamma=5.0, dt=0.05, so=api.SO_PX_SX)
+    with pytest.raises(SSGPError):
+        g.step_real(1)
+    g.close()
+
+
+def test_unitary_so_full_size_against_oracle():
+    """The 1024^2 real-time workload under the unitary-SO scheme, in the
+    launch shape the benchmark times (4 points per thread, full rows), two
+    calls against the oracle."""
+    w = W.W2D_REAL
+    psi0 = W.initial_2d_real(w)
+    prm = dict(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, so=w.so)
+    got = run(psi0, w.dx, False, w.dt, (1, 2), **prm)
+    cfg = oracle.Cfg(dim=2, nx=w.nx, ny=w.ny, dx=w.dx, dy=w.dy, imag=False, dt=w.dt, **prm)
+    want = oracle.step_unitary_so(cfg, psi0, 3)
+    assert rel(got, want) < 1e-10
