@@ -971,11 +971,15 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     store_row<R, KM, FULL>(dst, a.plane, nx, r, sh.xch[w]);
 }
 
-// (The unitary-SO form holds three coefficient sets per thread: from 2 points
-// per thread on it takes the registers of 2 wavefronts per SIMD.)
+// (The unitary-SO form holds three coefficient sets per thread: with
+// per-lane tables (CM = 0), or from 8 points per thread on, it takes the
+// registers of 2 wavefronts per SIMD; with 4 points and tabulated fix-ups it
+// keeps 4, which measured faster at 1024^2 than 2 without register spills:
+// 36.6 against 39.4 us.)
 template <typename R, int KM, int CM, bool FULL, bool SOY, bool USO = false>
 __global__ void __launch_bounds__(XPASS_THREADS)
-__attribute__((amdgpu_waves_per_eu(USO ? (KM <= 1 ? 4 : 2) : (KM <= 4 ? 4 : 1)))) xpass_kernel(XArgs<R> a) {
+__attribute__((amdgpu_waves_per_eu(USO ? (KM <= 1 || (KM <= 4 && CM != 0) ? 4 : 2) : (KM <= 4 ? 4 : 1))))
+xpass_kernel(XArgs<R> a) {
     __shared__ XShared<R, KM> sh;
     const int nx = FULL ? XPASS_THREADS * KM : a.nx;
     const int row = blockIdx.x;
