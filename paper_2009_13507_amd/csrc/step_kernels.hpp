@@ -975,10 +975,13 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
 // per-lane tables (CM = 0), or from 8 points per thread on, it takes the
 // registers of 2 wavefronts per SIMD; with 4 points and tabulated fix-ups it
 // keeps 4, which measured faster at 1024^2 than 2 without register spills:
-// 36.6 against 39.4 us.)
+// 36.6 against 39.4 us.  The y-derivative SO form at 4 points per thread
+// spills at 4 wavefronts per SIMD and runs faster at 2: 42.2 against 54.3 us
+// at 1024^2.)
 template <typename R, int KM, int CM, bool FULL, bool SOY, bool USO = false>
 __global__ void __launch_bounds__(XPASS_THREADS)
-__attribute__((amdgpu_waves_per_eu(USO ? (KM <= 1 || (KM <= 4 && CM != 0) ? 4 : 2) : (KM <= 4 ? 4 : 1))))
+__attribute__((amdgpu_waves_per_eu(USO ? (KM <= 1 || (KM <= 4 && CM != 0) ? 4 : 2)
+                                       : (KM <= 4 ? (SOY && KM == 4 ? 2 : 4) : 1))))
 xpass_kernel(XArgs<R> a) {
     __shared__ XShared<R, KM> sh;
     const int nx = FULL ? XPASS_THREADS * KM : a.nx;
