@@ -122,16 +122,17 @@ int ssgp_set_state(ssgp_grid g, void *psi_dev);
 int ssgp_set_params(ssgp_grid g, const ssgp_params *p);
 
 /* Selects the time-stepping scheme (default SSGP_SCHEME_PAPER).
- * SSGP_SCHEME_UNITARY_SO, for 2D grids with gamma p_x Sigma_x (or no SO):
- * each step is CALCNU, HERM, then one Crank-Nicolson solve of every row with
- * H_x = T (x) I + gamma (-i d_x) (x) S_x (the SO sub-step of Eqs. (p1)-(p2)
- * and LUX of Table 1 joined, S_x the spin-1 matrix of Eq. (3), central
- * differences, zero ghosts), then LUY and, in imaginary time, RENORM.  In
- * real time the step then conserves the norm exactly for gamma != 0.  The
- * library solves each row in the eigenbasis of S_x.  EINVAL for an unknown
- * scheme, a 1D grid, or parameters with another SO form (ssgp_set_params
- * then refuses those too); a step call returns EINVAL when the symmetrised
- * line matrix is not diagonally dominant (real time: dt gamma >= 2 dx).
+ * SSGP_SCHEME_UNITARY_SO, for the x-derivative SO forms (1D: gamma p_x
+ * Sigma_{x,y,z}; 2D: gamma p_x Sigma_x) or no SO: each step is CALCNU, HERM,
+ * then one Crank-Nicolson solve of every x line with
+ * H_x = T (x) I + gamma (-i d_x) (x) S_a (the SO sub-step of Eqs. (p1)-(p2)
+ * and LUX of Table 1 joined, S_a the spin-1 matrix of Eq. (3), central
+ * differences, zero ghosts), then LUY (2D) and, in imaginary time, RENORM.
+ * In real time the step then conserves the norm exactly for gamma != 0.  The
+ * library solves each line in the eigenbasis of S_a.  EINVAL for an unknown
+ * scheme or parameters with a y-derivative SO form (ssgp_set_params then
+ * refuses those too); a step call returns EINVAL when the symmetrised line
+ * matrix is not diagonally dominant (real time: dt gamma >= 2 dx).
  * The adjoint entry points (ssgp_step_real_seq, ssgp_step_real_adjoint)
  * return ESTATE under this scheme.  Drops the captured step graphs. */
 int ssgp_set_scheme(ssgp_grid g, int scheme);

@@ -17,7 +17,7 @@ from ._lib import Obs, Params, SSGPError, check
 SO_NONE, SO_PX_SX, SO_PX_SY, SO_PX_SZ, SO_RASHBA, SO_DRESSELHAUS, SO_ERD = range(7)
 RENORM_AUTO, RENORM_NORM, RENORM_FIXED_M = range(3)
 # PAPER: the paper's splitting; UNITARY_SO (opt-in): the SO term by
-# Crank-Nicolson together with the x kinetic term (2D, gamma p_x Sigma_x)
+# Crank-Nicolson together with the x kinetic term (the p_x Sigma forms)
 SCHEME_PAPER, SCHEME_UNITARY_SO = range(2)
 
 

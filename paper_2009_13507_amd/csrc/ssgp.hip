@@ -331,8 +331,8 @@ template <typename R> struct Tables {
     CNDev<R> x[NMODES];   // x lines as 64 chunks (1D, adjoint and batched rows)
     CNDev<R> xb[NMODES];  // x lines as 256 chunks (2D x-pass)
     CNDev<R> y[NMODES];
-    CNDev<R> xu[NMODES][3];  // unitary-SO scheme: the three symmetrised lines
-    DevBuf ramp[NMODES];     //   and their phase ramps [3][nx]
+    CNDev<R> xu[NMODES][3];  // unitary-SO scheme: the three symmetrised lines (as x in
+    DevBuf ramp[NMODES];     //   1D, as xb in 2D) and their phase ramps [3][nx]
 };
 
 struct ssgp_grid_s : GridCore {
@@ -357,8 +357,8 @@ template <> Tables<double> &tables<double>(ssgp_grid g) { return g->t64; }
 template <> Tables<float> &tables<float>(ssgp_grid g) { return g->t32; }
 
 // ------------------------------------------------- unitary-SO scheme --
-// gamma p_x S_x is solved together with CN_x: the line operator is
-// H = T (x) I + (-i d_x) (x) gamma S_x.  With S_x = W diag(1, 0, -1) W^H,
+// gamma p_x S_a (a = x, y, z) is solved together with CN_x: the line operator
+// is H = T (x) I + (-i d_x) (x) gamma S_a.  With S_a = W diag(1, 0, -1) W^H,
 // component c of W^H psi is the scalar line problem (I + sH_c) psi' =
 // (I - sH_c) psi, H_c = T + gamma lambda_c (-i d_x): tridiagonal Toeplitz
 // with diagonal d = 1 + s/h^2, upper u = s(-1/(2h^2) - i gamma lambda_c/(2h))
@@ -367,29 +367,43 @@ template <> Tables<float> &tables<float>(ssgp_grid g) { return g->t32; }
 // D = diag(rho^i), D^-1 (I + sH_c) D = tridiag(o, d, o) with o = u rho (and
 // the right-hand-side matrix 2I - (I + sH_c) transforms alike).  The line is
 // solved as CN_x is, on conj(rho^i) (W^H psi)_c, and multiplied back by rho^i.
-static void sx_eigen(cd W[9], double lam[3]) {
+// Eigenvectors (columns of W, row-major W[j][c]) of the spin matrix of the
+// p_x form, for the eigenvalues 1, 0, -1; the identity without SO.
+static void so_eigen(int so, cd W[9], double lam[3], cd S[9]) {
     const double r = 1.0 / std::sqrt(2.0);
-    const cd w[9] = {0.5, r, 0.5, r, 0.0, -r, 0.5, -r, 0.5};  // W[j][c], row-major
-    for (int q = 0; q < 9; ++q) W[q] = w[q];
-    lam[0] = 1.0;
+    const cd I(0.0, 1.0);
+    const cd wx[9] = {0.5, r, 0.5, r, 0.0, -r, 0.5, -r, 0.5};
+    const cd wy[9] = {0.5, r, 0.5, I * r, 0.0, -I * r, -0.5, r, -0.5};
+    const cd wz[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    cd Sx[9], Sy[9], Sz[9];
+    spin_matrices(Sx, Sy, Sz);
+    const cd *w = so == SSGP_SO_PX_SX ? wx : so == SSGP_SO_PX_SY ? wy : wz;
+    const cd *m = so == SSGP_SO_PX_SX ? Sx : so == SSGP_SO_PX_SY ? Sy : Sz;
+    const bool none = so != SSGP_SO_PX_SX && so != SSGP_SO_PX_SY && so != SSGP_SO_PX_SZ;
+    for (int q = 0; q < 9; ++q) {
+        W[q] = w[q];
+        S[q] = none ? cd(0.0) : m[q];
+    }
+    lam[0] = none ? 0.0 : 1.0;
     lam[1] = 0.0;
-    lam[2] = -1.0;
+    lam[2] = none ? 0.0 : -1.0;
 }
 
-template <typename R> static int build_uso(ssgp_grid g, int mode, int km) {
+// Tables of the three symmetrised lines (chunks of L points, nchunks per
+// line) and the phase ramps.
+template <typename R> static int build_uso(ssgp_grid g, int mode, int L, int nchunks) {
     Tables<R> &T = tables<R>(g);
-    cd W[9], Sx[9], Sy[9], Sz[9];
+    cd W[9], S[9];
     double lam[3];
-    sx_eigen(W, lam);
-    spin_matrices(Sx, Sy, Sz);
-    for (int j = 0; j < 3; ++j)  // W diag(lam) W^H must give S_x back
+    so_eigen(g->p.so, W, lam, S);
+    for (int j = 0; j < 3; ++j)  // W diag(lam) W^H must give the spin matrix back
         for (int k = 0; k < 3; ++k) {
             cd m = 0.0;
             for (int c = 0; c < 3; ++c) m += W[3 * j + c] * lam[c] * std::conj(W[3 * k + c]);
-            if (std::abs(m - Sx[3 * j + k]) > 1e-15) return fail(SSGP_EDEVICE, "S_x eigenvectors inconsistent");
+            if (std::abs(m - S[3 * j + k]) > 1e-15) return fail(SSGP_EDEVICE, "spin eigenvectors inconsistent");
         }
     for (int q = 0; q < 9; ++q) g->uso_rot[q] = W[q];
-    const double h = g->dx, gam = g->p.so == SSGP_SO_PX_SX ? g->p.gamma : 0.0;
+    const double h = g->dx, gam = g->p.gamma;
     const cd s = cn_s(mode, g->p.dt), I(0.0, 1.0);
     const cd d = 1.0 + s / (h * h);
     CNHost tab[3];
@@ -403,7 +417,7 @@ template <typename R> static int build_uso(ssgp_grid g, int mode, int km) {
         const cd o = u * rho;
         if (!(std::abs(d) > 2.0 * std::abs(o)))
             return fail(SSGP_EINVAL, "unitary SO: the line matrix is not diagonally dominant (dt gamma too large)");
-        tab[c] = cn_tables_do(g->nx, d, o, (2.0 - d) / o, km, XPASS_THREADS, 6);
+        tab[c] = cn_tables_do(g->nx, d, o, (2.0 - d) / o, L, nchunks, 6);
         levels = std::max(levels, tab[c].levels);
         const double th = std::arg(rho);
         for (int i = 0; i < g->nx; ++i)
@@ -411,7 +425,7 @@ template <typename R> static int build_uso(ssgp_grid g, int mode, int km) {
     }
     for (int c = 0; c < 3; ++c) {
         tab[c].levels = levels;
-        SSGP_TRY(upload_cn<R>(T.xu[mode][c], tab[c], g->nx, km, XPASS_THREADS, g->stream));
+        SSGP_TRY(upload_cn<R>(T.xu[mode][c], tab[c], g->nx, L, nchunks, g->stream));
     }
     SSGP_TRY(T.ramp[mode].ensure(ramp.size() * sizeof(cx<R>)));
     HIP_TRY(hipMemcpyAsync(T.ramp[mode].p, ramp.data(), ramp.size() * sizeof(cx<R>), hipMemcpyHostToDevice, g->stream));
@@ -426,6 +440,8 @@ template <typename R> static int build_tables(ssgp_grid g, int mode) {
     const cd s = cn_s(mode, g->p.dt);
     const int Lx = x_chunk(g->nx);
     SSGP_TRY(upload_cn<R>(T.x[mode], cn_tables(g->nx, g->dx, s, Lx, 64, 6), g->nx, Lx, 64, g->stream));
+    const bool uso = g->scheme == SSGP_SCHEME_UNITARY_SO && mode != MODE_ADJ;
+    if (g->dim == 1 && uso) SSGP_TRY(build_uso<R>(g, mode, Lx, 64));
     if (g->dim == 2) {
         const int km = x_block(g->nx);
         SSGP_TRY(upload_cn<R>(T.xb[mode], cn_tables(g->nx, g->dx, s, km, XPASS_THREADS, 6), g->nx, km, XPASS_THREADS,
@@ -435,7 +451,7 @@ template <typename R> static int build_tables(ssgp_grid g, int mode) {
         while ((YTX << maxlv) < 64) ++maxlv;
         SSGP_TRY(upload_cn<R>(T.y[mode], cn_tables(g->ny, g->dy, s, ys.L, ys.P, maxlv), g->ny, ys.L, ys.P,
                               g->stream));
-        if (g->scheme == SSGP_SCHEME_UNITARY_SO && mode != MODE_ADJ) SSGP_TRY(build_uso<R>(g, mode, km));
+        if (uso) SSGP_TRY(build_uso<R>(g, mode, km, XPASS_THREADS));
     }
     g->built_mode_mask |= 1 << mode;
     return SSGP_OK;
@@ -707,6 +723,16 @@ template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int
     a.qxmask = tmp.qxmask;
     a.sp = renorm_spec(*g);
     a.renorm_out = g->renorm.as<double>();
+    a.ramp = nullptr;
+    if (g->scheme == SSGP_SCHEME_UNITARY_SO && mode != MODE_ADJ) {
+        a.ramp = T.ramp[mode].template as<cx<R>>();
+        for (int q = 0; q < 9; ++q) a.rot[q] = tor<R>(g->uso_rot[q]);
+        for (int c = 0; c < 3; ++c) {
+            a.cu[c] = T.xu[mode][c].coef();
+            a.rdiag_u[c] = T.xu[mode][c].rdiag;
+        }
+        a.qxmask = 0;  // the SO term is in the line solve
+    }
     LAUNCH_TRY(launch_step1d<R>(lc(*g), a, x_chunk(g->nx)));
     return SSGP_OK;
 }
@@ -790,8 +816,8 @@ static int check_params(const GridCore &g, const ssgp_params *p) {
     if (g.dim == 2 && (p->so == SSGP_SO_PX_SY || p->so == SSGP_SO_PX_SZ))
         return fail(SSGP_EINVAL, "SO form %d is defined for 1D grids", p->so);
     if (std::fabs(p->mag0) > 1.0) return fail(SSGP_EINVAL, "|mag0| must be <= 1");
-    if (g.scheme == SSGP_SCHEME_UNITARY_SO && p->so != SSGP_SO_NONE && p->so != SSGP_SO_PX_SX)
-        return fail(SSGP_EINVAL, "the unitary-SO scheme takes gamma p_x Sigma_x (or no SO)");
+    if (g.scheme == SSGP_SCHEME_UNITARY_SO && so_has_y(p->so))
+        return fail(SSGP_EINVAL, "the unitary-SO scheme takes the p_x Sigma forms (or no SO)");
     return SSGP_OK;
 }
 
@@ -864,11 +890,8 @@ extern "C" int ssgp_set_scheme(ssgp_grid g, int scheme) {
     if (!g) return fail(SSGP_EINVAL, "grid is NULL");
     if (scheme != SSGP_SCHEME_PAPER && scheme != SSGP_SCHEME_UNITARY_SO)
         return fail(SSGP_EINVAL, "unknown scheme %d", scheme);
-    if (scheme == SSGP_SCHEME_UNITARY_SO) {
-        if (g->dim != 2) return fail(SSGP_EINVAL, "the unitary-SO scheme is for 2D grids");
-        if (g->have_params && g->p.so != SSGP_SO_NONE && g->p.so != SSGP_SO_PX_SX)
-            return fail(SSGP_EINVAL, "the unitary-SO scheme takes gamma p_x Sigma_x (or no SO)");
-    }
+    if (scheme == SSGP_SCHEME_UNITARY_SO && g->have_params && so_has_y(g->p.so))
+        return fail(SSGP_EINVAL, "the unitary-SO scheme takes the p_x Sigma forms (or no SO)");
     if (scheme != g->scheme) {
         g->clear_graphs();
         g->built_mode_mask = 0;

@@ -1195,9 +1195,17 @@ template <typename R> struct Args1D {
     unsigned qxmask;
     RenormSpec sp;
     double *renorm_out;        // last step's {d, N, fallback}, or nullptr
+    // unitary-SO scheme, as in XArgs (line j of the rotated state uses cu[j])
+    const cx<R> *ramp;         // [3][nx], or nullptr
+    cx<R> rot[9];
+    LineCoef<R> cu[3];
+    cx<R> rdiag_u[3];
 };
 
-template <typename R, int L, int CM>
+// USO: the unitary-SO scheme (each wavefront solves its line of the state
+// rotated into the SO spin matrix's eigenbasis and phase-symmetrised; the
+// state is rotated back in LDS before the RENORM norms).
+template <typename R, int L, int CM, bool USO = false>
 __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
     extern __shared__ unsigned char smem_raw[];
     cx<R> *s = reinterpret_cast<cx<R> *>(smem_raw);
@@ -1223,15 +1231,44 @@ __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
             cx<R> p = s[si], z = s[ld + si], m = s[2 * ld + si];
             const R xv = a.x0 + R(i) * a.dx;
             pointwise(p, z, m, R(0.5) * xv * xv, a.m);
+            if constexpr (USO) {
+                const cx<R> v[3] = {p, z, m};
+                cx<R> w[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    w[c] = conj(a.ramp[c * nx + i]) *
+                           (conj(a.rot[c]) * v[0] + conj(a.rot[3 + c]) * v[1] + conj(a.rot[6 + c]) * v[2]);
+                p = w[0];
+                z = w[1];
+                m = w[2];
+            }
             s[si] = p;
             s[ld + si] = z;
             s[2 * ld + si] = m;
         }
         __syncthreads();
         cx<R> r[L];
-        build_rhs_any<R, L>(j, s, nullptr, ld, nx, start, len, a.qx, a.qxmask, a.rdiag, r);
+        build_rhs_any<R, L>(j, s, nullptr, ld, nx, start, len, a.qx, a.qxmask, USO ? a.rdiag_u[j] : a.rdiag, r);
         __syncthreads();
-        solve_line_wave<R, L, CM>(r, start, len, a.cx_);
+        solve_line_wave<R, L, CM>(r, start, len, USO ? a.cu[j] : a.cx_);
+        if constexpr (USO) {
+            cx<R> *wj = s + j * ld;
+#pragma unroll
+            for (int t = 0; t < L; ++t)
+                if (t < len) wj[sidx<L>(start + t)] = a.ramp[j * nx + start + t] * r[t];
+            __syncthreads();
+            for (int i = tid; i < nx; i += ROW_THREADS) {
+                const int si = sidx<L>(i);
+                const cx<R> w0 = s[si], w1 = s[ld + si], w2 = s[2 * ld + si];
+                s[si] = a.rot[0] * w0 + a.rot[1] * w1 + a.rot[2] * w2;
+                s[ld + si] = a.rot[3] * w0 + a.rot[4] * w1 + a.rot[5] * w2;
+                s[2 * ld + si] = a.rot[6] * w0 + a.rot[7] * w1 + a.rot[8] * w2;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < L; ++t)
+                if (t < len) r[t] = wj[sidx<L>(start + t)];
+        }
         if (a.m.imag) {
             double nrm = 0.0;
 #pragma unroll

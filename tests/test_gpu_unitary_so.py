@@ -3,7 +3,9 @@ together with LUX, solved per row in the eigenbasis of S_x) against the
 oracle's definition of it: relative L2 <= 1e-10 in FP64 and <= 1e-5 in FP32
 over every x-pass shape (1, 2, 4 and 8 points per thread, full and ragged
 rows), in real and imaginary time; exact real-time norm; graph replays
-bitwise equal to one-by-one launches; and the refusals."""
+bitwise equal to one-by-one launches; and the refusals.  1D grids (the
+LDS-resident kernel) with the three p_x Sigma forms against the oracle, and
+the Table 3 SO-coupled 1D energy reached under this scheme too."""
 import numpy as np
 import pytest
 
@@ -127,11 +129,6 @@ def test_switching_schemes():
 
 
 def test_unitary_so_refusals():
-    t1 = torch.from_numpy(W.gaussian(1, 64, 1, 0.1, 0.1)).to(DEV)
-    g1 = api.Grid(t1, 0.1)
-    with pytest.raises(SSGPError):
-        g1.set_scheme(api.SCHEME_UNITARY_SO)          # 1D grid
-    g1.close()
     nx, ny, dx = 64, 48, 0.1
     t = torch.from_numpy(start(nx, ny, dx, 9)).to(DEV)
     g = api.Grid(t, dx, dx)
@@ -164,3 +161,47 @@ def test_unitary_so_full_size_against_oracle():
     cfg = oracle.Cfg(dim=2, nx=w.nx, ny=w.ny, dx=w.dx, dy=w.dy, imag=False, dt=w.dt, **prm)
     want = oracle.step_unitary_so(cfg, psi0, 3)
     assert rel(got, want) < 1e-10
+
+
+@pytest.mark.parametrize("imag", [False, True], ids=["real", "imag"])
+@pytest.mark.parametrize("so", [api.SO_PX_SX, api.SO_PX_SY, api.SO_PX_SZ], ids=["Sx", "Sy", "Sz"])
+@pytest.mark.parametrize("nx", [100, 512, 640, 2048])
+def test_unitary_so_1d_matches_oracle(nx, so, imag):
+    dx, dt = 0.05, 5e-4
+    base = W.gaussian(1, nx, 1, dx, dx, phases=(0.3, 1.1, 2.0), width=0.15 * nx * dx)
+    psi0 = base * (1 + W.random_state(base.shape, nx, 0.05))
+    prm = dict(c0=30.0, c2=-2.0, gamma=0.7, omega=0.15, so=so)
+    print(f"unitary SO 1D nx={nx} so={so} imag={imag}", flush=True)
+    t = torch.from_numpy(psi0.copy()).to(DEV)
+    g = api.Grid(t, dx)
+    g.set_params(dt=dt, **prm)
+    g.set_scheme(api.SCHEME_UNITARY_SO)
+    for n in (3, 1, 4):
+        (g.step_imag if imag else g.step_real)(n)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    n1 = g.observables()["N"]
+    g.close()
+    cfg = oracle.Cfg(dim=1, nx=nx, ny=1, dx=dx, dy=dx, imag=imag, dt=dt, **prm)
+    want = oracle.step_unitary_so(cfg, psi0, 8)
+    assert rel(got, want) < 1e-10
+    if not imag:
+        assert abs(n1 - float(np.sum(np.abs(psi0) ** 2) * dx)) < 1e-13
+
+
+def test_unitary_so_1d_table3_energy():
+    """Table 3, 1D polar, gamma p_x Sigma_x with gamma = 0.5 (DX = 0.05,
+    DT = 0.00025, 640 points): the imaginary-time relaxation under the
+    unitary-SO scheme reaches the printed 15.12354 as the paper's scheme does
+    (tolerance 5e-5)."""
+    nx, dx = 640, 0.05
+    t = torch.from_numpy(W.gaussian(1, nx, 1, dx, dx, weights=(0.25, 0.5, 0.25), width=3.0)).to(DEV)
+    g = api.Grid(t, dx)
+    g.set_params(c0=241.0, c2=7.5, gamma=0.5, so=api.SO_PX_SX, dt=2.5e-4)
+    g.set_scheme(api.SCHEME_UNITARY_SO)
+    for _ in range(7):
+        g.step_imag(100000)
+        o = g.observables()
+        print(f"  E = {o['E']:.8f}", flush=True)
+    g.close()
+    assert abs(o["E"] - 15.12354) < 5e-5, o["E"]
