@@ -277,3 +277,23 @@ def step_unitary_so(cfg: Cfg, psi, nsteps: int = 1) -> np.ndarray:
         if cfg.imag:
             a, _ = renorm(cfg, a)
     return a
+
+
+
+# -------------------------------------------- RENORM in real time (opt-in) --
+# App. A keeps the norm (and, under Eq. (DJ), the magnetisation) by rescaling
+# the components after each time step of the propagation; the sample real-time
+# output of Sec. 3 holds its energy constant over 90,000 steps, as it does when
+# the rule is applied after every real-time step too.  The plain step above
+# renormalises in imaginary time only.
+
+def step_real_renorm(cfg: Cfg, psi, nsteps: int = 1, unitary_so: bool = False) -> np.ndarray:
+    """nsteps real-time steps (the paper's scheme, or the unitary-SO one),
+    each followed by the RENORM rule of Eqs. (DJ)/(DJ2)."""
+    if cfg.imag:
+        raise ValueError("real time only")
+    a = _arr(cfg, psi)
+    for _ in range(int(nsteps)):
+        a = step_unitary_so(cfg, a, 1) if unitary_so else step(cfg, a, 1)
+        a, _ = renorm(cfg, a)
+    return a
