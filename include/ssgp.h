@@ -137,6 +137,16 @@ int ssgp_set_params(ssgp_grid g, const ssgp_params *p);
  * return ESTATE under this scheme.  Drops the captured step graphs. */
 int ssgp_set_scheme(ssgp_grid g, int scheme);
 
+/* on = 1: apply the RENORM rule (Eqs. (DJ)/(DJ2), as chosen by the renorm
+ * parameter) after every real-time step as well, as App. A does after each
+ * time step of the propagation; the sample real-time output of Sec. 3 keeps
+ * its energy constant that way.  on = 0 (default): real-time steps are not
+ * rescaled, so the norm and magnetisation can be tracked.  Either scheme.
+ * EINVAL for another value.  While on, the adjoint entry points
+ * (ssgp_step_real_seq, ssgp_step_real_adjoint) return ESTATE.  Drops the
+ * captured step graphs. */
+int ssgp_set_renorm_real(ssgp_grid g, int on);
+
 /* Piecewise-constant Rabi control for real-time steps: the step with index
  * n (see ssgp_set_step_index) uses omega[n / steps_per_seg] (clamped to the
  * last segment).  nseg = 0 removes the schedule (then params.omega is used).

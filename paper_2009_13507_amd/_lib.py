@@ -65,6 +65,7 @@ def load():
         "ssgp_set_state": ([G, vp], ci),
         "ssgp_set_params": ([G, ctypes.POINTER(Params)], ci),
         "ssgp_set_scheme": ([G, ci], ci),
+        "ssgp_set_renorm_real": ([G, ci], ci),
         "ssgp_set_omega_schedule": ([G, ctypes.POINTER(cd), ci, ci], ci),
         "ssgp_set_step_index": ([G, cll], ci),
         "ssgp_get_step_index": ([G], cll),

@@ -101,6 +101,10 @@ class Grid:
     def set_scheme(self, scheme: int):
         check(self._lib.ssgp_set_scheme(self._h, int(scheme)))
 
+    def set_renorm_real(self, on: bool):
+        """RENORM after every real-time step too (off by default)."""
+        check(self._lib.ssgp_set_renorm_real(self._h, 1 if on else 0))
+
     def set_omega_schedule(self, omega, steps_per_seg: int):
         arr = (ctypes.c_double * len(omega))(*[float(v) for v in omega])
         check(self._lib.ssgp_set_omega_schedule(self._h, arr, len(omega), int(steps_per_seg)))

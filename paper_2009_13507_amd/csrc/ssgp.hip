@@ -314,6 +314,9 @@ struct GridCore {
     hipStream_t cap = nullptr;
     int scheme = SSGP_SCHEME_PAPER;
     cd uso_rot[9];  // unitary-SO scheme: eigenvectors of the SO spin matrix (columns)
+    bool renorm_real = false;  // RENORM after every real-time step as well
+    // steps of this mode end with the RENORM rule
+    bool renorms(int mode) const { return mode == MODE_IMAG || (mode == MODE_REAL && renorm_real); }
     void clear_graphs() {
         if (graphs.empty()) return;
         (void)hipStreamSynchronize(stream);  // no replay of them still in flight
@@ -582,14 +585,14 @@ template <typename R> static int adjoint_steps(ssgp_grid g, const void *states, 
 static int ew_blocks(long long n) { return (int)std::min<long long>((n + 255) / 256, 2048); }
 
 // One 2D step from src into dst (dst may equal src except with a
-// y-derivative SO form).  Imaginary time: with renorm_prev the RENORM of the
-// previous step (whose y-pass left its tile partials in g->partials) is
-// applied first, reduced inside the x-pass; the y-pass leaves this step's
-// partials.
+// y-derivative SO form).  Imaginary time (and real time with renorm_real):
+// with renorm_prev the RENORM of the previous step (whose y-pass left its
+// tile partials in g->partials) is applied first, reduced inside the x-pass;
+// the y-pass leaves this step's partials.
 template <typename R>
 static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omega, bool renorm_prev) {
-    const bool imag = mode == MODE_IMAG;
-    renorm_prev = renorm_prev && imag;
+    const bool rn = g->renorms(mode);
+    renorm_prev = renorm_prev && rn;
     hipEvent_t *ev = nullptr;
     if (g->prof_every > 0 && (g->prof_counter++ % g->prof_every) == 0 && g->prof_used < g->prof_cap)
         ev = &g->prof_events[(size_t)4 * g->prof_used++];
@@ -631,7 +634,7 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
         }
         SSGP_TRY(launch_x<R>(*g, xa, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     }
-    YArgs<R> ya = y_args<R>(g, mode, dst, imag ? g->partials.as<double>() : nullptr);
+    YArgs<R> ya = y_args<R>(g, mode, dst, rn ? g->partials.as<double>() : nullptr);
     SSGP_TRY(launch_y<R>(*g, ya, ys, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
     return SSGP_OK;
 }
@@ -657,7 +660,7 @@ static int step_graph(ssgp_grid g, int mode, int k, bool renorm_first, double om
     hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         for (int s = 0; s < k && rc == SSGP_OK; ++s)
-            rc = step2d<R>(g, mode, g->psi, g->psi, omega, mode == MODE_IMAG && (renorm_first || s > 0));
+            rc = step2d<R>(g, mode, g->psi, g->psi, omega, g->renorms(mode) && (renorm_first || s > 0));
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(g->cap, &graph);
         if (e == hipSuccess && rc == SSGP_OK) {
@@ -680,16 +683,17 @@ static int step_graph(ssgp_grid g, int mode, int k, bool renorm_first, double om
 // n in-place 2D steps of g->psi at a fixed Omega.  Runs of steps go out as
 // graph replays (runs of 2^i <= 64 steps), except steps whose kernels are
 // timed and the y-derivative SO forms (their extra pass copies the state),
-// which are launched one by one.  Imaginary time: every step but (unless
-// renorm_first) the first applies the previous step's RENORM.
+// which are launched one by one.  Imaginary time (and real time with
+// renorm_real): every step but (unless renorm_first) the first applies the
+// previous step's RENORM.
 template <typename R> static int run_steps(ssgp_grid g, int mode, int n, double omega, bool renorm_first) {
-    if (mode != MODE_IMAG) renorm_first = false;
+    if (!g->renorms(mode)) renorm_first = false;
     const bool graphable = g->dim == 2 && !(so_has_y(g->p.so) && g->p.gamma != 0.0);
     int s = 0;
     while (s < n) {
         const bool timing = g->prof_every > 0 && g->prof_used < g->prof_cap;
         if (!graphable || (timing && g->prof_counter % g->prof_every == 0)) {
-            SSGP_TRY(step2d<R>(g, mode, g->psi, g->psi, omega, mode == MODE_IMAG && (renorm_first || s > 0)));
+            SSGP_TRY(step2d<R>(g, mode, g->psi, g->psi, omega, g->renorms(mode) && (renorm_first || s > 0)));
             ++s;
             continue;
         }
@@ -698,7 +702,7 @@ template <typename R> static int run_steps(ssgp_grid g, int mode, int n, double 
         int p = 1;
         while (p * 2 <= std::min(k, STEP_GRAPH_MAX)) p *= 2;
         hipGraphExec_t exec = nullptr;
-        SSGP_TRY(step_graph<R>(g, mode, p, mode == MODE_IMAG && (renorm_first || s > 0), omega, &exec));
+        SSGP_TRY(step_graph<R>(g, mode, p, g->renorms(mode) && (renorm_first || s > 0), omega, &exec));
         HIP_TRY(hipGraphLaunch(exec, g->stream));
         if (g->prof_every > 0) g->prof_counter += p;
         s += p;
@@ -723,6 +727,7 @@ template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int
     a.qxmask = tmp.qxmask;
     a.sp = renorm_spec(*g);
     a.renorm_out = g->renorm.as<double>();
+    a.renorm = g->renorms(mode) ? 1 : 0;
     a.ramp = nullptr;
     if (g->scheme == SSGP_SCHEME_UNITARY_SO && mode != MODE_ADJ) {
         a.ramp = T.ramp[mode].template as<cx<R>>();
@@ -737,17 +742,20 @@ template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int
     return SSGP_OK;
 }
 
+// The RENORM of the last 2D step of a call (its y-pass left the partials).
+template <typename R> static int final_renorm(ssgp_grid g) {
+    LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), (g->nx + YTX - 1) / YTX, renorm_spec(*g),
+                                      g->renorm.as<double>()));
+    LAUNCH_TRY(launch_scale<R>(lc(*g), static_cast<cx<R> *>(g->psi), plane_of(*g), g->renorm.as<double>(),
+                               ew_blocks(plane_of(*g))));
+    return SSGP_OK;
+}
+
 template <typename R> static int step_imag_t(ssgp_grid g, int nsteps) {
     SSGP_TRY(build_tables<R>(g, MODE_IMAG));
     if (g->dim == 1) return launch_1d<R>(g, MODE_IMAG, g->psi, nsteps, g->p.omega);
     SSGP_TRY(run_steps<R>(g, MODE_IMAG, nsteps, g->p.omega, false));
-    if (nsteps > 0) {
-        // the last step's RENORM
-        LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), (g->nx + YTX - 1) / YTX,
-                                          renorm_spec(*g), g->renorm.as<double>()));
-        LAUNCH_TRY(launch_scale<R>(lc(*g), static_cast<cx<R> *>(g->psi), plane_of(*g), g->renorm.as<double>(),
-                                   ew_blocks(plane_of(*g))));
-    }
+    if (nsteps > 0) SSGP_TRY(final_renorm<R>(g));
     return SSGP_OK;
 }
 
@@ -786,10 +794,13 @@ template <typename R> static int step_real_t(ssgp_grid g, const void *src, void 
                 const long long seg_end = (n / g->steps_per_seg + 1) * g->steps_per_seg;
                 chunk = (int)std::min<long long>(chunk, seg_end - n);
             }
-            SSGP_TRY(run_steps<R>(g, MODE_REAL, chunk, omega_at(*g, g->step_index), false));
+            // (with renorm_real, a run after the first applies the RENORM
+            // that the run before it left)
+            SSGP_TRY(run_steps<R>(g, MODE_REAL, chunk, omega_at(*g, g->step_index), done > 0));
             g->step_index += chunk;
             done += chunk;
         }
+        if (g->renorm_real && nsteps > 0) SSGP_TRY(final_renorm<R>(g));
         return SSGP_OK;
     }
     const cx<R> *cur = static_cast<const cx<R> *>(src);
@@ -900,6 +911,16 @@ extern "C" int ssgp_set_scheme(ssgp_grid g, int scheme) {
     return SSGP_OK;
 }
 
+extern "C" int ssgp_set_renorm_real(ssgp_grid g, int on) {
+    if (!g) return fail(SSGP_EINVAL, "grid is NULL");
+    if (on != 0 && on != 1) return fail(SSGP_EINVAL, "on must be 0 or 1");
+    if ((on != 0) != g->renorm_real) {
+        g->clear_graphs();  // the graphs hold the y-pass partials and RENORM reductions or not
+        g->renorm_real = on != 0;
+    }
+    return SSGP_OK;
+}
+
 extern "C" int ssgp_set_omega_schedule(ssgp_grid g, const double *omega, int nseg, int steps_per_seg) {
     if (!g) return fail(SSGP_EINVAL, "grid is NULL");
     if (nseg < 0 || (nseg > 0 && (!omega || steps_per_seg < 1))) return fail(SSGP_EINVAL, "bad schedule");
@@ -940,7 +961,8 @@ extern "C" int ssgp_step_real(ssgp_grid g, int nsteps) {
 extern "C" int ssgp_step_real_seq(ssgp_grid g, const void *src, void *dst, int nsteps) {
     if (!g || !src || !dst) return fail(SSGP_EINVAL, "NULL argument");
     if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
-    if (g->scheme != SSGP_SCHEME_PAPER) return fail(SSGP_ESTATE, "the adjoint path follows the paper's scheme");
+    if (g->scheme != SSGP_SCHEME_PAPER || g->renorm_real)
+        return fail(SSGP_ESTATE, "the adjoint path follows the paper's scheme without real-time RENORM");
     if (nsteps < 0) return fail(SSGP_EINVAL, "nsteps < 0");
     return g->dtype == SSGP_C128 ? step_real_t<double>(g, src, dst, nsteps, true)
                                  : step_real_t<float>(g, src, dst, nsteps, true);
@@ -999,7 +1021,8 @@ extern "C" int ssgp_observables(ssgp_grid g, ssgp_obs *out) {
 extern "C" int ssgp_step_real_adjoint(ssgp_grid g, const void *states_dev, void *lambda_dev, int nsteps) {
     if (!g || !states_dev || !lambda_dev) return fail(SSGP_EINVAL, "NULL argument");
     if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
-    if (g->scheme != SSGP_SCHEME_PAPER) return fail(SSGP_ESTATE, "the adjoint path follows the paper's scheme");
+    if (g->scheme != SSGP_SCHEME_PAPER || g->renorm_real)
+        return fail(SSGP_ESTATE, "the adjoint path follows the paper's scheme without real-time RENORM");
     if (nsteps < 0) return fail(SSGP_EINVAL, "nsteps < 0");
     return g->dtype == SSGP_C128 ? adjoint_steps<double>(g, states_dev, lambda_dev, nsteps)
                                  : adjoint_steps<float>(g, states_dev, lambda_dev, nsteps);

@@ -1194,6 +1194,8 @@ template <typename R> struct Args1D {
     cx<R> qx[9];
     unsigned qxmask;
     RenormSpec sp;
+    int renorm;                // 1: the RENORM rule after every step (imaginary
+                               // time; real time when asked for)
     double *renorm_out;        // last step's {d, N, fallback}, or nullptr
     // unitary-SO scheme, as in XArgs (line j of the rotated state uses cu[j])
     const cx<R> *ramp;         // [3][nx], or nullptr
@@ -1269,7 +1271,7 @@ __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
             for (int t = 0; t < L; ++t)
                 if (t < len) r[t] = wj[sidx<L>(start + t)];
         }
-        if (a.m.imag) {
+        if (a.renorm) {
             double nrm = 0.0;
 #pragma unroll
             for (int t = 0; t < L; ++t)
@@ -1306,7 +1308,7 @@ __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
         a.psi[nx + i] = s[ld + si];
         a.psi[2 * nx + i] = s[2 * ld + si];
     }
-    if (a.renorm_out && tid < 7 && a.m.imag && a.nsteps > 0) a.renorm_out[tid] = dsh[tid];
+    if (a.renorm_out && tid < 7 && a.renorm && a.nsteps > 0) a.renorm_out[tid] = dsh[tid];
 }
 
 } // namespace ssgp

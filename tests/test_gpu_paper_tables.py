@@ -139,15 +139,13 @@ def test_sample_real_time_output_2d_rashba():
     """The 2D sample output of Sec. 3 (real time, Rashba gamma = 0.5, c0 =
     482, c2 = 15, DX = DY = 0.1, DT = 0.00025, NPAS = 80000 then NRUN = 10000
     steps from the imaginary-time state; 161 points a side there, 160 here,
-    which also puts x = 0 on a grid point).  At the first print the energy is
-    8.1969 and the rms sizes 3.469, 2.194, 3.469; M prints 0 throughout.
-    Checked: E at the first print (1e-4), RAD of the 0 component (printed to
-    three decimals), RAD(+1) = RAD(-1), M = 0 through the run, and every RAD
-    within 2.5e-3 of its print at all three prints (the +-1 radii of the
-    relaxed state sit 1e-3 above the printed 3.469, and the prints move by
-    1e-3 between them).  The printed E stays at 8.1969 to the end; with the
-    explicit SO sub-step the norm here grows by 5e-4 over the run, so E is
-    not compared past the first print."""
+    which also puts x = 0 on a grid point).  App. A rescales the components
+    after each time step, in real time too (ssgp_set_renorm_real); so done,
+    the energy stays at the printed 8.1969 at all three prints (1e-4), M at
+    0, and every rms size within 2e-3 of its print (the +-1 radii of the
+    relaxed state sit 1e-3 above the printed 3.469; the prints move by 1e-3
+    between them).  The radius of the 0 component at the first print is
+    checked to its printed three decimals."""
     n, dx = 160, 0.1
     prm = dict(c0=482.0, c2=15.0, gamma=0.5, so=api.SO_RASHBA)
     t = torch.from_numpy(W.so_trial(n, n, dx, dx, api.SO_RASHBA, 0.5, 15.0, width=2.0)).to("cuda:0")
@@ -155,6 +153,7 @@ def test_sample_real_time_output_2d_rashba():
     g.set_params(dt=5e-4, **prm)
     g.step_imag(120000)
     g.set_params(dt=2.5e-4, **prm)
+    g.set_renorm_real(True)
     prints = [("NSTP", 0, (3.469, 2.194, 3.469)), ("NPAS", 80000, (3.468, 2.193, 3.468)),
               ("NRUN", 10000, (3.469, 2.195, 3.469))]
     for name, steps, rad in prints:
@@ -162,13 +161,14 @@ def test_sample_real_time_output_2d_rashba():
             g.step_real(steps)
         o = g.observables()
         got = (o["rms+1"], o["rms0"], o["rms-1"])
-        print(f"  {name}: RAD {got[0]:.5f} {got[1]:.5f} {got[2]:.5f}  E {o['E']:.6f}  M {o['M']:.1e}  N {o['N']:.8f}",
+        print(f"  {name}: RAD {got[0]:.5f} {got[1]:.5f} {got[2]:.5f}  E {o['E']:.6f}  M {o['M']:.1e}  N {o['N']:.12f}",
               flush=True)
+        assert abs(o["E"] - 8.1969) < 1e-4, (name, o["E"])
+        assert abs(o["N"] - 1.0) < 1e-12
         if name == "NSTP":
-            assert abs(o["E"] - 8.1969) < 1e-4
             assert abs(got[1] - 2.194) < 5e-4
         assert abs(got[0] - got[2]) < 1e-10
         assert abs(o["M"]) < 1e-12
         for a, b in zip(got, rad):
-            assert abs(a - b) < 2.5e-3, (name, got)
+            assert abs(a - b) < 2e-3, (name, got)
     g.close()
