@@ -60,3 +60,46 @@ def test_ground_state_is_dynamically_stable(name, dim, n, dx, c0, c0q, c2, so, r
         else:
             assert abs(o["E"] - e1) < 1e-3 * abs(e1)
     g.close()
+
+
+# The same two runs at the paper's full length and real-time steps (Sec. 4:
+# DT = DX^2 * 0.05 in 1D, DX^2 * 0.025 in 2D; t = 200), with the RENORM rule
+# after every real-time step as the paper's programs apply it (App. A),
+# checked at the times of Fig. 4 (t = 50, 100, 150, 200): every component
+# density within 10% of its ground-state peak, M = 0, N = 1, and E constant
+# to 1e-3 relative between the prints.
+FULL = [  # name, dim, n, dx, c0 -> c0', c2, so, relax steps, relax dt, real-time dt
+    ("1D ferro gamma p_x Sigma_x", 1, 640, 0.05, 885.0, 920.0, -4.1, api.SO_PX_SX, 300000, 2.5e-4, 1.25e-4),
+    ("2D polar Rashba", 2, 256, 0.1, 482.0, 500.0, 15.0, api.SO_RASHBA, 120000, 5e-4, 2.5e-4),
+]
+
+
+@pytest.mark.parametrize("name,dim,n,dx,c0,c0q,c2,so,relax,rdt,dt", FULL, ids=[c[0] for c in FULL])
+def test_fig4_runs_to_t200(name, dim, n, dx, c0, c0q, c2, so, relax, rdt, dt):
+    base = W.gaussian(dim, n, n, dx, dx, width=3.0 if dim == 1 else 2.0)
+    if dim == 2:
+        base = W.so_trial(n, n, dx, dx, so, 0.5, c2, width=2.0)
+    psi = torch.from_numpy(base).to("cuda:0")
+    g = api.Grid(psi, dx, dx if dim == 2 else None)
+    g.set_params(c0=c0, c2=c2, gamma=0.5, so=so, dt=rdt)
+    g.step_imag(relax)
+    rho0 = densities(psi)
+    g.set_params(c0=c0q, c2=c2, gamma=0.5, so=so, dt=dt)
+    g.set_renorm_real(True)
+    per = int(round(50.0 / dt))
+    e1 = None
+    for k in range(4):
+        g.step_real(per)
+        o = g.observables()
+        r = densities(psi)
+        dev = max(np.abs(r[j] - rho0[j]).max() / rho0[j].max() for j in range(3))
+        print(f"  t = {50 * (k + 1)}: N = {o['N']:.12f}, M = {o['M']:+.1e}, E = {o['E']:.7f}, "
+              f"max density change {dev:.4f}", flush=True)
+        assert dev < 0.10, (name, k, dev)
+        assert abs(o["M"]) < 1e-12
+        assert abs(o["N"] - 1.0) < 1e-12
+        if e1 is None:
+            e1 = o["E"]
+        else:
+            assert abs(o["E"] - e1) < 1e-3 * abs(e1)
+    g.close()
