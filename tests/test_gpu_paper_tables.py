@@ -19,14 +19,29 @@ from paper_2009_13507_amd import workloads as W  # noqa: E402
 
 NX, DX, DT = 640, 0.05, 2.5e-4
 
-TABLE4 = [  # (name, c0, c2, m, weights, printed E)
+def _polar_w(m):
+    return ((1 + m) / 2 - 0.05, 0.1, (1 - m) / 2 - 0.05)
+
+
+def _ferro_w(m):
+    return ((1 + m) ** 2 / 4, (1 - m * m) / 2, (1 - m) ** 2 / 4)
+
+
+TABLE4 = [  # (name, c0, c2, m, weights, printed E): every 1D "spinor" entry
     ("polar m=0", 241.0, 7.5, 0.0, (0.49, 0.02, 0.49), 15.2485),
     ("polar m=0.1", 241.0, 7.5, 0.1, (0.55, 0.0, 0.45), 15.2514),
+    ("polar m=0.2", 241.0, 7.5, 0.2, _polar_w(0.2), 15.2599),
     ("polar m=0.3", 241.0, 7.5, 0.3, (0.6, 0.1, 0.3), 15.2743),
+    ("polar m=0.4", 241.0, 7.5, 0.4, _polar_w(0.4), 15.2945),
+    ("polar m=0.5", 241.0, 7.5, 0.5, _polar_w(0.5), 15.3209),
     ("polar m=0.6", 241.0, 7.5, 0.6, (0.8, 0.0, 0.2), 15.3537),
     ("ferro m=0", 885.0, -4.1, 0.0, (0.25, 0.5, 0.25), 36.1365),
+    ("ferro m=0.1", 885.0, -4.1, 0.1, _ferro_w(0.1), 36.1365),
     ("ferro m=0.2", 885.0, -4.1, 0.2, (0.36, 0.48, 0.16), 36.1365),
+    ("ferro m=0.3", 885.0, -4.1, 0.3, _ferro_w(0.3), 36.1365),
+    ("ferro m=0.4", 885.0, -4.1, 0.4, _ferro_w(0.4), 36.1365),
     ("ferro m=0.5", 885.0, -4.1, 0.5, (0.5625, 0.375, 0.0625), 36.1365),
+    ("ferro m=0.6", 885.0, -4.1, 0.6, _ferro_w(0.6), 36.1365),
 ]
 
 
@@ -71,8 +86,19 @@ def test_table3_so_coupled_energies(name, c0, c2, steps, printed):
 # used.)
 TABLE4_2D = [  # (name, c0, c2, gamma, so, m, weights, steps, printed E)
     ("2D polar m=0", 482.0, 15.0, 0.0, api.SO_NONE, 0.0, (0.49, 0.02, 0.49), 40000, 8.3605),
+    ("2D polar m=0.1", 482.0, 15.0, 0.0, api.SO_NONE, 0.1, _polar_w(0.1), 40000, 8.3617),
+    ("2D polar m=0.2", 482.0, 15.0, 0.0, api.SO_NONE, 0.2, _polar_w(0.2), 40000, 8.3652),
     ("2D polar m=0.3", 482.0, 15.0, 0.0, api.SO_NONE, 0.3, (0.6, 0.1, 0.3), 40000, 8.3710),
+    ("2D polar m=0.4", 482.0, 15.0, 0.0, api.SO_NONE, 0.4, _polar_w(0.4), 40000, 8.3793),
+    ("2D polar m=0.5", 482.0, 15.0, 0.0, api.SO_NONE, 0.5, _polar_w(0.5), 40000, 8.3900),
+    ("2D polar m=0.6", 482.0, 15.0, 0.0, api.SO_NONE, 0.6, _polar_w(0.6), 40000, 8.4033),
     ("2D ferro m=0", 1327.5, -6.15, 0.0, api.SO_NONE, 0.0, (0.25, 0.5, 0.25), 40000, 13.7420),
+    ("2D ferro m=0.1", 1327.5, -6.15, 0.0, api.SO_NONE, 0.1, _ferro_w(0.1), 40000, 13.7420),
+    ("2D ferro m=0.2", 1327.5, -6.15, 0.0, api.SO_NONE, 0.2, _ferro_w(0.2), 40000, 13.7420),
+    ("2D ferro m=0.3", 1327.5, -6.15, 0.0, api.SO_NONE, 0.3, _ferro_w(0.3), 40000, 13.7420),
+    ("2D ferro m=0.4", 1327.5, -6.15, 0.0, api.SO_NONE, 0.4, _ferro_w(0.4), 40000, 13.7420),
+    ("2D ferro m=0.5", 1327.5, -6.15, 0.0, api.SO_NONE, 0.5, _ferro_w(0.5), 40000, 13.7420),
+    ("2D ferro m=0.6", 1327.5, -6.15, 0.0, api.SO_NONE, 0.6, _ferro_w(0.6), 40000, 13.7420),
     ("2D polar Rashba gamma=0.5", 482.0, 15.0, 0.5, api.SO_RASHBA, 0.0, (0.25, 0.5, 0.25), 120000, 8.19690),
 ]
 
