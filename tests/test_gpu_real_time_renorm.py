@@ -164,3 +164,21 @@ def test_refusals():
     with pytest.raises(SSGPError):
         g.step_real_seq(t, torch.empty((1,) + tuple(t.shape), dtype=t.dtype, device=DEV), 1)
     g.close()
+
+
+def test_2d_complex64():
+    nx, ny, dx = 128, 96, 0.1
+    prm = dict(c0=2.0, c2=-0.3, gamma=0.7, omega=0.15, dt=2e-3, so=api.SO_PX_SX)
+    psi0 = start2d(nx, ny, dx, 6)
+    t = torch.from_numpy(psi0.copy()).to(DEV, torch.complex64)
+    g = api.Grid(t, dx, dx)
+    g.set_params(**prm)
+    g.set_renorm_real(True)
+    g.step_real(20)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy().astype(np.complex128)
+    o = g.observables()
+    g.close()
+    cfg = oracle.Cfg(dim=2, nx=nx, ny=ny, dx=dx, dy=dx, imag=False, **prm)
+    assert rel(got, oracle.step_real_renorm(cfg, psi0, 20)) < 1e-5
+    assert abs(o["N"] - 1.0) < 1e-6

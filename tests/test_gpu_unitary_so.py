@@ -205,3 +205,19 @@ def test_unitary_so_1d_table3_energy():
         print(f"  E = {o['E']:.8f}", flush=True)
     g.close()
     assert abs(o["E"] - 15.12354) < 5e-5, o["E"]
+
+
+def test_unitary_so_1d_complex64():
+    nx, dx, dt = 640, 0.05, 5e-4
+    base = W.gaussian(1, nx, 1, dx, dx, phases=(0.3, 1.1, 2.0), width=4.0)
+    prm = dict(c0=30.0, c2=-2.0, gamma=0.7, omega=0.15, so=api.SO_PX_SY)
+    t = torch.from_numpy(base.copy()).to(DEV, torch.complex64)
+    g = api.Grid(t, dx)
+    g.set_params(dt=dt, **prm)
+    g.set_scheme(api.SCHEME_UNITARY_SO)
+    g.step_real(12)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy().astype(np.complex128)
+    g.close()
+    cfg = oracle.Cfg(dim=1, nx=nx, ny=1, dx=dx, dy=dx, imag=False, dt=dt, **prm)
+    assert rel(got, oracle.step_unitary_so(cfg, base, 12)) < 1e-5
