@@ -21,7 +21,8 @@ def test_header_declares_the_boundary():
     names = _lib.exported_names()
     for required in ("ssgp_create_grid", "ssgp_set_params", "ssgp_step_imag", "ssgp_step_real",
                      "ssgp_observables", "ssgp_step_real_adjoint", "ssgp_create_batch",
-                     "ssgp_batch_step_imag", "ssgp_destroy", "ssgp_last_error"):
+                     "ssgp_batch_step_imag", "ssgp_destroy", "ssgp_last_error", "ssgp_set_scheme",
+                     "ssgp_set_renorm_real"):
         assert required in names
 
 
@@ -58,6 +59,8 @@ def test_create_grid_rejects_bad_arguments(lib, args, fragment):
 
 def test_null_arguments(lib):
     assert lib.ssgp_create_grid(2, 8, 8, 0.1, 0.1, 0, None, None, None) == _lib.EINVAL
+    assert lib.ssgp_set_scheme(None, 1) == _lib.EINVAL
+    assert lib.ssgp_set_renorm_real(None, 1) == _lib.EINVAL
     h = ctypes.c_void_p()
     assert lib.ssgp_create_grid(2, 8, 8, 0.1, 0.1, 0, None, None, ctypes.byref(h)) == _lib.EINVAL
     assert lib.ssgp_step_imag(None, 1) == _lib.EINVAL
