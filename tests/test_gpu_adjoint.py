@@ -132,3 +132,50 @@ def test_autograd_central_differences():
         e[s] = h
         fd = (loss_of(base_p, om.detach() + e) - loss_of(base_p, om.detach() - e)) / (2 * h)
         assert abs(fd - go[s]) < 1e-6 * max(1.0, abs(fd)), (s, fd, go[s])
+
+
+def test_central_differences_on_the_512_workload():
+    """The differentiable workload at full size (512^2, 2000 real-time steps,
+    100 Omega segments, checkpoints every 45 steps): gradients within 1e-6 of
+    central differences with h = 1e-6 for Omega segments and for the real and
+    imaginary parts of psi_0 where its gradient is largest; and, with h =
+    1e-5, within 1e-6 relative for psi_0 and 1e-3 relative for Omega (whose
+    gradients, about 3e-8, sit where the rounding of the loss difference,
+    about 1e-16 L / h, allows no closer check)."""
+    w = W.W2D_ADJ
+    psi0 = W.interpolate(W.ground_256(), W.W2D_IMAG.nx, W.W2D_IMAG.dx, w.nx, w.dx)
+    omega = W.omega_schedule(100, seed=2)
+    prob = autograd.RealTimeProblem(dx=w.dx, dy=w.dy, dt=w.dt, steps=w.steps, steps_per_seg=w.steps // 100,
+                                    c0=w.c0, c2=w.c2, gamma=w.gamma, so=w.so)
+    p0 = torch.from_numpy(psi0).to(DEV).requires_grad_(True)
+    om = torch.tensor(omega, dtype=torch.float64, device=DEV, requires_grad=True)
+    out = autograd.propagate(p0, om, prob)
+    (w.dx * w.dy * (out[0].abs() ** 2).sum()).backward()
+    gp = p0.grad.cpu().numpy().reshape(-1)
+    go = om.grad.cpu().numpy()
+    base = torch.from_numpy(psi0).to(DEV)
+
+    def loss(p, o):
+        with torch.no_grad():
+            r = autograd.propagate(p, o, prob)
+            return float(w.dx * w.dy * (r[0].abs() ** 2).sum())
+
+    q = int(np.abs(gp).argmax())
+    for h, rel_psi, rel_om in ((1e-6, None, None), (1e-5, 1e-6, 1e-3)):
+        for s in (0, 50, 99):
+            e = torch.zeros(100, dtype=torch.float64, device=DEV)
+            e[s] = h
+            fd = (loss(base, om.detach() + e) - loss(base, om.detach() - e)) / (2 * h)
+            print(f"  h={h} Omega[{s}]: fd {fd:.6e}, adjoint {go[s]:.6e}", flush=True)
+            assert abs(fd - go[s]) < 1e-6 * max(1.0, abs(fd))
+            if rel_om:
+                assert abs(fd - go[s]) < rel_om * abs(go[s])
+        for unit, part in ((1.0, np.real), (1j, np.imag)):
+            e = torch.zeros(gp.size, dtype=torch.complex128, device=DEV)
+            e[q] = h * unit
+            e = e.reshape(base.shape)
+            fd = (loss(base + e, om.detach()) - loss(base - e, om.detach())) / (2 * h)
+            print(f"  h={h} psi0[{q}]: fd {fd:.9e}, adjoint {part(gp[q]):.9e}", flush=True)
+            assert abs(fd - part(gp[q])) < 1e-6 * max(1.0, abs(fd))
+            if rel_psi:
+                assert abs(fd - part(gp[q])) < rel_psi * abs(part(gp[q]))
