@@ -16,8 +16,9 @@ Prints one JSON line:
   cpu_baseline  the CPU oracle on the host cores, on a bounded sample of the
              same workload (first steps from the same initial state).
 Beside them: the forward+adjoint cost ratio, the batched-vs-serial
-comparison, the imaginary-time workloads, and the same 1024^2 workload under
-the opt-in unitary-SO scheme (unitary_so).
+comparison, the imaginary-time workloads, the same 1024^2 workload under the
+opt-in unitary-SO scheme (unitary_so) and in complex64 (complex64_step, with
+its difference from complex128).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -183,6 +184,42 @@ def unitary_so(steps: int = 1000, warmup: int = 50, every: int = 7):
             "norm_change": n1 - n0}
 
 
+def complex64_step(steps: int = 1000, warmup: int = 50):
+    """The 1024^2 real-time workload in complex64 (FP32 storage and
+    arithmetic): step rate, and the relative L2 difference from the same
+    steps in complex128."""
+    import torch
+
+    from paper_2009_13507_amd import api
+    from paper_2009_13507_amd import workloads as W
+
+    w = W.W2D_REAL
+    psi0 = W.initial_2d_real(w)
+    out = {}
+    for name, dt in (("c64", torch.complex64), ("c128", torch.complex128)):
+        warm = torch.from_numpy(psi0).to("cuda:0").to(dt)
+        g = api.Grid(warm, w.dx, w.dy)
+        g.set_params(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, dt=w.dt, so=w.so)
+        g.step_real(warmup)
+        g.close()
+        state = torch.from_numpy(psi0).to("cuda:0").to(dt)
+        g = api.Grid(state, w.dx, w.dy)
+        g.set_params(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, dt=w.dt, so=w.so)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step_real(steps)
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0, state.to(torch.complex128))
+        g.close()
+    el, s64 = out["c64"]
+    ref = out["c128"][1]
+    npts = w.nx * w.ny
+    return {"workload": w.name + " (complex64)", "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "pt_steps_per_s": npts * steps / el,
+            "hbm_frac_step_algorithmic": 2 * BYTES_PER_PT_PASS["f32"] * npts * steps / el / (HBM_PEAK_GBS * 1e9),
+            "rel_l2_vs_complex128": float(torch.linalg.vector_norm(s64 - ref) / torch.linalg.vector_norm(ref))}
+
+
 def batch_compare(steps: int = 200, warmup: int = 20):
     """The 64-instance imaginary-time batch (sizes 128..512, seed-1 draw):
     batched (autotuned launch shape, graph replay) against one grid at a
@@ -342,6 +379,8 @@ def main():
         line["adjoint_cost_ratio"] = adjoint_ratio()
     if not args.no_uso and args.dtype == "f64":
         line["unitary_so"] = unitary_so()
+    if not args.no_batch and args.dtype == "f64":
+        line["complex64_step"] = complex64_step()
     if not args.no_batch:
         line["batch_c4"] = batch_compare()
         line["imag_workloads"] = imag_workloads()
