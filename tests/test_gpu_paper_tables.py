@@ -198,3 +198,26 @@ def test_sample_real_time_output_2d_rashba():
         for a, b in zip(got, rad):
             assert abs(a - b) < 2e-3, (name, got)
     g.close()
+
+
+# Table 3's finest 2D column (DX = DY < 0.05 there; 0.05 here, 512^2 over the
+# same box, DT = DX^2 * 0.1 = 0.00025): Rashba gamma = 0.5 from the vortex
+# trial states of Sec. 3, printed to five decimals: tolerance 5e-5.
+@pytest.mark.parametrize("name,c0,c2,steps,printed,m", [
+    ("ferro", 1327.5, -6.15, 300000, 13.59761, 0.0468),
+    ("polar", 482.0, 15.0, 180000, 8.19690, 0.0),
+])
+def test_table3_2d_fine_grid(name, c0, c2, steps, printed, m):
+    n, dx = 512, 0.05
+    t = torch.from_numpy(W.so_trial(n, n, dx, dx, api.SO_RASHBA, 0.5, c2, width=2.0)).to("cuda:0")
+    g = api.Grid(t, dx, dx)
+    g.set_params(c0=c0, c2=c2, gamma=0.5, so=api.SO_RASHBA, dt=2.5e-4)
+    done = 0
+    while done < steps:
+        g.step_imag(60000)
+        done += 60000
+        o = g.observables()
+        print(f"  {done} steps: E = {o['E']:.8f}, M = {o['M']:.5f}", flush=True)
+    g.close()
+    assert abs(o["E"] - printed) < 5e-5, (name, o["E"])
+    assert abs(o["M"] - m) < 1e-3, (name, o["M"])
