@@ -599,13 +599,12 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
     const YShape ys = y_shape(g->ny);
     const int ntiles = (g->nx + YTX - 1) / YTX;
     if (so_has_y(g->p.so) && g->p.gamma != 0.0) {
-        // pointwise pass in place on src's copy in scratch, then SO(x,y) + CN_x
+        // pointwise pass from src into scratch, then SO(x,y) + CN_x from scratch
         const size_t bytes = (size_t)3 * plane_of(*g) * sizeof(cx<R>);
         SSGP_TRY(g->scratch.ensure(bytes));
-        if (src != g->scratch.p)
-            HIP_TRY(hipMemcpyAsync(g->scratch.p, src, bytes, hipMemcpyDeviceToDevice, g->stream));
         PArgs<R> pa{};
         pa.psi = g->scratch.as<cx<R>>();
+        pa.src = src == g->scratch.p ? nullptr : static_cast<const cx<R> *>(src);
         pa.nx = g->nx;
         pa.ny = g->ny;
         pa.plane = plane_of(*g);

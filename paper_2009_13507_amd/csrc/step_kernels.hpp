@@ -1139,9 +1139,11 @@ __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
 
 // ------------------------------------------------ pointwise-only pass ---
 // Used ahead of an x-pass that reads neighbouring rows (y-derivative SO):
-// RENORM scale, CALCNU and HERM in place.
+// RENORM scale, CALCNU and HERM, from src (or in place when src is null)
+// into psi.
 template <typename R> struct PArgs {
     cx<R> *psi;
+    const cx<R> *src;
     int nx, ny;
     long long plane;
     R dx, dy, x0, y0;
@@ -1155,7 +1157,8 @@ __global__ void __launch_bounds__(256) pointwise_kernel(PArgs<R> a) {
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x) {
         const int ix = (int)(q % a.nx), iy = (int)(q / a.nx);
-        cx<R> p = a.psi[q], z = a.psi[n + q], m = a.psi[2 * n + q];
+        const cx<R> *in = a.src ? a.src : a.psi;
+        cx<R> p = in[q], z = in[n + q], m = in[2 * n + q];
         if (a.dscale) {
             p = R(a.dscale[0]) * p;
             z = R(a.dscale[1]) * z;
