@@ -383,6 +383,25 @@ __device__ __forceinline__ void wave_scan_down(cx<R> &A, cx<R> &B, int levels) {
     }
 }
 
+// The same with the lane's coefficients and chunk product already in registers.
+template <typename R, int L>
+__device__ __forceinline__ void solve_line_cached(cx<R> (&r)[L], int len, const ChunkCoef<R, L, 0> &cpl, cx<R> Ak,
+                                                  int levels) {
+    const int lane = threadIdx.x & 63;
+    cx<R> A = Ak;
+    cx<R> B = fwd_local<R, L>(r, len, cpl);
+    wave_scan_up<R, 1>(A, B, levels);
+    cx<R> carry = shfl_up(B, 1);
+    if (lane == 0) carry = czero<R>();
+    fwd_fix<R, L>(r, len, cpl, carry);
+    A = Ak;
+    B = bwd_local<R, L>(r, len, cpl);
+    wave_scan_down<R, 1>(A, B, levels);
+    carry = shfl_down(B, 1);
+    if (lane == 63) carry = czero<R>();
+    bwd_fix<R, L>(r, len, cpl, carry);
+}
+
 // Solves one line held by the 64 lanes of a wavefront (lane k owns
 // [start, start+len)).
 template <typename R, int L, int CM>
@@ -541,7 +560,9 @@ template <typename R> struct XArgs {
 };
 
 constexpr int XPASS_THREADS = 256;
-constexpr int ROW_THREADS = 192;  // 1D kernel: 3 wavefronts, one per component line
+// 1D kernel: wavefronts 0-2 solve the three component lines; all of them
+// share the pointwise work (more wavefronts where the chunk registers allow)
+__host__ __device__ constexpr int step1d_threads(int L) { return L >= 16 ? 256 : 512; }
 
 // Whole-wavefront rotations by one lane (DPP wave_ror:1 / wave_rol:1):
 // ror1 gives lane l the value of lane l-1 (lane 0 gets lane 63), rol1 the
@@ -1210,8 +1231,11 @@ template <typename R> struct Args1D {
 // USO: the unitary-SO scheme (each wavefront solves its line of the state
 // rotated into the SO spin matrix's eigenbasis and phase-symmetrised; the
 // state is rotated back in LDS before the RENORM norms).
-template <typename R, int L, int CM, bool USO = false>
-__global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
+// The line-solve coefficients are read once into registers (per-lane
+// pivots, CM = 0 form): they do not change during the run.
+template <typename R, int L, bool USO = false>
+__global__ void __launch_bounds__(step1d_threads(L)) step1d_kernel(Args1D<R> a) {
+    constexpr int NT = step1d_threads(L);
     extern __shared__ unsigned char smem_raw[];
     cx<R> *s = reinterpret_cast<cx<R> *>(smem_raw);
     __shared__ double red[3];
@@ -1223,15 +1247,22 @@ __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
     const int start = lane * L;
     const int len = max(0, min(L, nx - start));
 
-    for (int i = tid; i < nx; i += ROW_THREADS) {
+    for (int i = tid; i < nx; i += NT) {
         const int si = sidx<L>(i);
         s[si] = a.psi[i];
         s[ld + si] = a.psi[nx + i];
         s[2 * ld + si] = a.psi[2 * nx + i];
     }
     __syncthreads();
+    // this lane's elimination coefficients and chunk product, read once for
+    // the whole run (the tables do not change between steps)
+    const int jc = j < 3 ? j : 0;
+    const LineCoef<R> &lc = USO ? a.cu[jc] : a.cx_;
+    const ChunkCoef<R, L, 0> ccache(lc, start);
+    const cx<R> Acache = lc.chunkA[lane];
+    const int lvcache = lc.levels;
     for (int step = 0; step < a.nsteps; ++step) {
-        for (int i = tid; i < nx; i += ROW_THREADS) {
+        for (int i = tid; i < nx; i += NT) {
             const int si = sidx<L>(i);
             cx<R> p = s[si], z = s[ld + si], m = s[2 * ld + si];
             const R xv = a.x0 + R(i) * a.dx;
@@ -1252,17 +1283,23 @@ __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
             s[2 * ld + si] = m;
         }
         __syncthreads();
+        const bool solver = j < 3;  // wavefront-uniform
+        const int jj = solver ? j : 0;
         cx<R> r[L];
-        build_rhs_any<R, L>(j, s, nullptr, ld, nx, start, len, a.qx, a.qxmask, USO ? a.rdiag_u[j] : a.rdiag, r);
+        if (solver)
+            build_rhs_any<R, L>(jj, s, nullptr, ld, nx, start, len, a.qx, a.qxmask, USO ? a.rdiag_u[jj] : a.rdiag,
+                                r);
         __syncthreads();
-        solve_line_wave<R, L, CM>(r, start, len, USO ? a.cu[j] : a.cx_);
+        if (solver) solve_line_cached<R, L>(r, len, ccache, Acache, lvcache);
         if constexpr (USO) {
-            cx<R> *wj = s + j * ld;
+            cx<R> *wj = s + jj * ld;
+            if (solver) {
 #pragma unroll
-            for (int t = 0; t < L; ++t)
-                if (t < len) wj[sidx<L>(start + t)] = a.ramp[j * nx + start + t] * r[t];
+                for (int t = 0; t < L; ++t)
+                    if (t < len) wj[sidx<L>(start + t)] = a.ramp[jj * nx + start + t] * r[t];
+            }
             __syncthreads();
-            for (int i = tid; i < nx; i += ROW_THREADS) {
+            for (int i = tid; i < nx; i += NT) {
                 const int si = sidx<L>(i);
                 const cx<R> w0 = s[si], w1 = s[ld + si], w2 = s[2 * ld + si];
                 s[si] = a.rot[0] * w0 + a.rot[1] * w1 + a.rot[2] * w2;
@@ -1270,18 +1307,22 @@ __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
                 s[2 * ld + si] = a.rot[6] * w0 + a.rot[7] * w1 + a.rot[8] * w2;
             }
             __syncthreads();
+            if (solver) {
 #pragma unroll
-            for (int t = 0; t < L; ++t)
-                if (t < len) r[t] = wj[sidx<L>(start + t)];
+                for (int t = 0; t < L; ++t)
+                    if (t < len) r[t] = wj[sidx<L>(start + t)];
+            }
         }
         if (a.renorm) {
-            double nrm = 0.0;
+            if (solver) {
+                double nrm = 0.0;
 #pragma unroll
-            for (int t = 0; t < L; ++t)
-                if (t < len) nrm += (double)abs2(r[t]);
+                for (int t = 0; t < L; ++t)
+                    if (t < len) nrm += (double)abs2(r[t]);
 #pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) nrm += __shfl_down(nrm, d, 64);
-            if (lane == 0) red[j] = nrm;
+                for (int d = 32; d >= 1; d >>= 1) nrm += __shfl_down(nrm, d, 64);
+                if (lane == 0) red[jj] = nrm;
+            }
             __syncthreads();
             if (tid == 0) {
                 double N[3] = {red[0] * a.sp.dA, red[1] * a.sp.dA, red[2] * a.sp.dA};
@@ -1294,18 +1335,22 @@ __global__ void __launch_bounds__(ROW_THREADS) step1d_kernel(Args1D<R> a) {
                 dsh[6] = fb;
             }
             __syncthreads();
-            const R dj = R(dsh[j]);
+            if (solver) {
+                const R dj = R(dsh[jj]);
+#pragma unroll
+                for (int t = 0; t < L; ++t)
+                    if (t < len) r[t] = dj * r[t];
+            }
+        }
+        if (solver) {
+            cx<R> *wj = s + jj * ld;
 #pragma unroll
             for (int t = 0; t < L; ++t)
-                if (t < len) r[t] = dj * r[t];
+                if (t < len) wj[sidx<L>(start + t)] = r[t];
         }
-        cx<R> *wj = s + j * ld;
-#pragma unroll
-        for (int t = 0; t < L; ++t)
-            if (t < len) wj[sidx<L>(start + t)] = r[t];
         __syncthreads();
     }
-    for (int i = tid; i < nx; i += ROW_THREADS) {
+    for (int i = tid; i < nx; i += NT) {
         const int si = sidx<L>(i);
         a.psi[i] = s[si];
         a.psi[nx + i] = s[ld + si];
