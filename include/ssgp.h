@@ -123,7 +123,8 @@ int ssgp_set_params(ssgp_grid g, const ssgp_params *p);
 
 /* Selects the time-stepping scheme (default SSGP_SCHEME_PAPER).
  * SSGP_SCHEME_UNITARY_SO, for the x-derivative SO forms (1D: gamma p_x
- * Sigma_{x,y,z}; 2D: gamma p_x Sigma_x) or no SO: each step is CALCNU, HERM,
+ * Sigma_{x,y,z}; 2D: gamma p_x Sigma_x and the equal mixture, which is
+ * -gamma p_x Sigma_y) or no SO: each step is CALCNU, HERM,
  * then one Crank-Nicolson solve of every x line with
  * H_x = T (x) I + gamma (-i d_x) (x) S_a (the SO sub-step of Eqs. (p1)-(p2)
  * and LUX of Table 1 joined, S_a the spin-1 matrix of Eq. (3), central

@@ -219,7 +219,8 @@ def num_threads() -> int:
 # gamma != 0.  Written from the definition: for every x line,
 #   (I + s H) psi' = (I - s H) psi,  H = I_3 (x) T + gamma S_a (x) (-i D),
 # T = -1/2 d^2/dx^2 and D = d/dx by the three-point and central stencils with
-# zero ghosts, S_a the spin-1 matrix of Eq. (3) of the p_x Sigma_a form, and
+# zero ghosts, S_a the spin-1 matrix of Eq. (3) of the p_x Sigma_a form (the
+# equal mixture of Rashba and Dresselhaus couplings is -gamma p_x Sigma_y), and
 # s = i dt/2 in real time, dt/2 in imaginary time (Delta -> -i Delta).  The
 # line vector is component-major (psi_{+1}(x_0..), psi_0(..), psi_{-1}(..)).
 
@@ -242,9 +243,13 @@ def _line_hamiltonian(cfg: Cfg):
     D = sp.diags([np.full(n - 1, -0.5 / h), np.full(n - 1, 0.5 / h)], [-1, 1])
     H = sp.kron(sp.identity(3), T)
     if cfg.so != SO_NONE and cfg.gamma != 0.0:
-        if cfg.so not in _SPIN:
-            raise ValueError("the unitary-SO scheme takes the p_x Sigma_a forms")
-        H = H + sp.kron(cfg.gamma * _SPIN[cfg.so], -1j * D)
+        if cfg.so == SO_ERD:      # gamma (0 p_y Sigma_x - p_x Sigma_y): x derivatives only
+            M = -cfg.gamma * _SPIN[SO_PX_SY]
+        elif cfg.so in _SPIN:
+            M = cfg.gamma * _SPIN[cfg.so]
+        else:
+            raise ValueError("the unitary-SO scheme takes the forms without y derivatives")
+        H = H + sp.kron(M, -1j * D)
     return sp.csc_matrix(H, dtype=complex)
 
 

@@ -398,7 +398,9 @@ template <typename R> static int build_uso(ssgp_grid g, int mode, int L, int nch
     Tables<R> &T = tables<R>(g);
     cd W[9], S[9];
     double lam[3];
-    so_eigen(g->p.so, W, lam, S);
+    // the equal mixture is -gamma p_x Sigma_y
+    const bool erd = g->p.so == SSGP_SO_ERD;
+    so_eigen(erd ? SSGP_SO_PX_SY : g->p.so, W, lam, S);
     for (int j = 0; j < 3; ++j)  // W diag(lam) W^H must give the spin matrix back
         for (int k = 0; k < 3; ++k) {
             cd m = 0.0;
@@ -406,7 +408,7 @@ template <typename R> static int build_uso(ssgp_grid g, int mode, int L, int nch
             if (std::abs(m - S[3 * j + k]) > 1e-15) return fail(SSGP_EDEVICE, "spin eigenvectors inconsistent");
         }
     for (int q = 0; q < 9; ++q) g->uso_rot[q] = W[q];
-    const double h = g->dx, gam = g->p.gamma;
+    const double h = g->dx, gam = erd ? -g->p.gamma : g->p.gamma;
     const cd s = cn_s(mode, g->p.dt), I(0.0, 1.0);
     const cd d = 1.0 + s / (h * h);
     CNHost tab[3];
@@ -468,6 +470,9 @@ static bool uses_fixed_m(const ssgp_params &p) {
 }
 
 static bool so_has_y(int so) { return so == SSGP_SO_RASHBA || so == SSGP_SO_DRESSELHAUS || so == SSGP_SO_ERD; }
+// y-derivative terms present (the equal mixture, eta = 0, has none: its
+// coupling is -gamma p_x Sigma_y alone)
+static bool so_y_terms(int so) { return so == SSGP_SO_RASHBA || so == SSGP_SO_DRESSELHAUS; }
 
 static double omega_at(const GridCore &g, long long n) {
     if (g.omega_sched.empty()) return g.p.omega;
@@ -598,7 +603,7 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
         ev = &g->prof_events[(size_t)4 * g->prof_used++];
     const YShape ys = y_shape(g->ny);
     const int ntiles = (g->nx + YTX - 1) / YTX;
-    if (so_has_y(g->p.so) && g->p.gamma != 0.0) {
+    if (so_y_terms(g->p.so) && g->p.gamma != 0.0) {
         // pointwise pass from src into scratch, then SO(x,y) + CN_x from scratch
         const size_t bytes = (size_t)3 * plane_of(*g) * sizeof(cx<R>);
         SSGP_TRY(g->scratch.ensure(bytes));
@@ -687,7 +692,7 @@ static int step_graph(ssgp_grid g, int mode, int k, bool renorm_first, double om
 // previous step's RENORM.
 template <typename R> static int run_steps(ssgp_grid g, int mode, int n, double omega, bool renorm_first) {
     if (!g->renorms(mode)) renorm_first = false;
-    const bool graphable = g->dim == 2 && !(so_has_y(g->p.so) && g->p.gamma != 0.0);
+    const bool graphable = g->dim == 2 && !(so_y_terms(g->p.so) && g->p.gamma != 0.0);
     int s = 0;
     while (s < n) {
         const bool timing = g->prof_every > 0 && g->prof_used < g->prof_cap;
@@ -826,8 +831,8 @@ static int check_params(const GridCore &g, const ssgp_params *p) {
     if (g.dim == 2 && (p->so == SSGP_SO_PX_SY || p->so == SSGP_SO_PX_SZ))
         return fail(SSGP_EINVAL, "SO form %d is defined for 1D grids", p->so);
     if (std::fabs(p->mag0) > 1.0) return fail(SSGP_EINVAL, "|mag0| must be <= 1");
-    if (g.scheme == SSGP_SCHEME_UNITARY_SO && so_has_y(p->so))
-        return fail(SSGP_EINVAL, "the unitary-SO scheme takes the p_x Sigma forms (or no SO)");
+    if (g.scheme == SSGP_SCHEME_UNITARY_SO && so_y_terms(p->so))
+        return fail(SSGP_EINVAL, "the unitary-SO scheme takes the forms without y derivatives");
     return SSGP_OK;
 }
 
@@ -900,8 +905,8 @@ extern "C" int ssgp_set_scheme(ssgp_grid g, int scheme) {
     if (!g) return fail(SSGP_EINVAL, "grid is NULL");
     if (scheme != SSGP_SCHEME_PAPER && scheme != SSGP_SCHEME_UNITARY_SO)
         return fail(SSGP_EINVAL, "unknown scheme %d", scheme);
-    if (scheme == SSGP_SCHEME_UNITARY_SO && g->have_params && so_has_y(g->p.so))
-        return fail(SSGP_EINVAL, "the unitary-SO scheme takes the p_x Sigma forms (or no SO)");
+    if (scheme == SSGP_SCHEME_UNITARY_SO && g->have_params && so_y_terms(g->p.so))
+        return fail(SSGP_EINVAL, "the unitary-SO scheme takes the forms without y derivatives");
     if (scheme != g->scheme) {
         g->clear_graphs();
         g->built_mode_mask = 0;

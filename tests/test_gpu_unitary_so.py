@@ -140,7 +140,7 @@ def test_unitary_so_refusals():
     g.set_params(c0=1.0, gamma=0.5, dt=1e-3, so=api.SO_PX_SX)
     g.set_scheme(api.SCHEME_UNITARY_SO)
     with pytest.raises(SSGPError):
-        g.set_params(c0=1.0, gamma=0.5, dt=1e-3, so=api.SO_ERD)
+        g.set_params(c0=1.0, gamma=0.5, dt=1e-3, so=api.SO_DRESSELHAUS)
     with pytest.raises(SSGPError):
         g.step_real_seq(t, torch.empty((1,) + tuple(t.shape), dtype=t.dtype, device=DEV), 1)
     # dt gamma >= 2 dx: the symmetrised line matrix is not diagonally dominant
@@ -221,3 +221,17 @@ def test_unitary_so_1d_complex64():
     g.close()
     cfg = oracle.Cfg(dim=1, nx=nx, ny=1, dx=dx, dy=dx, imag=False, dt=dt, **prm)
     assert rel(got, oracle.step_unitary_so(cfg, base, 12)) < 1e-5
+
+
+
+@pytest.mark.parametrize("imag", [False, True], ids=["real", "imag"])
+@pytest.mark.parametrize("nx,ny", [(96, 40), (1024, 5)])
+def test_unitary_so_equal_mixture(nx, ny, imag):
+    """The equal mixture of Rashba and Dresselhaus couplings is -gamma p_x
+    Sigma_y: solved in the eigenbasis of S_y."""
+    dx, dt = 0.1, 2e-3
+    prm = dict(PRM, so=api.SO_ERD)
+    psi0 = start(nx, ny, dx, nx + 3)
+    got = run(psi0, dx, imag, dt, (3, 4), **prm)
+    cfg = oracle.Cfg(dim=2, nx=nx, ny=ny, dx=dx, dy=dx, imag=imag, dt=dt, **prm)
+    assert rel(got, oracle.step_unitary_so(cfg, psi0, 7)) < 1e-10

@@ -109,3 +109,15 @@ def test_rejects_forms_with_y_derivatives():
     c = cfg2(so=oracle.SO_RASHBA)
     with pytest.raises(ValueError):
         oracle.cn_x_so(c, W.random_state((3, c.ny, c.nx), 17))
+
+
+def test_equal_mixture_line_hamiltonian_is_the_c_oracles_hso():
+    """The equal mixture of Rashba and Dresselhaus couplings (eta = 0) has x
+    derivatives only; row by row, its line Hamiltonian's SO part is the C
+    oracle's H_SO of the 2D state."""
+    c = cfg2(nx=24, ny=6, so=oracle.SO_ERD, gamma=0.8)
+    c0 = cfg2(nx=24, ny=6, so=oracle.SO_ERD, gamma=0.0)
+    psi = W.random_state((3, c.ny, c.nx), 18)
+    Hd = (oracle._line_hamiltonian(c) - oracle._line_hamiltonian(c0))
+    rows = np.stack([(Hd @ psi[:, y, :].reshape(-1)).reshape(3, c.nx) for y in range(c.ny)], axis=1)
+    np.testing.assert_allclose(rows, oracle.apply_hso(c, psi), rtol=0, atol=1e-12)
