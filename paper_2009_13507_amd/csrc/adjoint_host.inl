@@ -2,7 +2,7 @@
 
 template <typename R>
 static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps) {
-    if (so_has_y(g->p.so) && g->p.gamma != 0.0)
+    if (so_y_terms(g->p.so) && g->p.gamma != 0.0)
         return fail(SSGP_EINVAL, "the adjoint supports SO forms with x derivatives only");
     SSGP_TRY(build_tables<R>(g, MODE_ADJ));
     const int rows = g->dim == 2 ? g->ny : 1;

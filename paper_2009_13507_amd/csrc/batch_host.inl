@@ -273,7 +273,7 @@ extern "C" int ssgp_create_batch(int n, const int *nx, const int *ny, const doub
             return fail(SSGP_EINVAL, "instance %d: nx and ny must be in [1, %d]", i, BATCH_MAX_N);
         if (!(dx[i] > 0) || !std::isfinite(dx[i])) return fail(SSGP_EINVAL, "instance %d: dx must be positive", i);
         if (offsets[i] < 0) return fail(SSGP_EINVAL, "instance %d: negative offset", i);
-        if (so_has_y(p[i].so) && p[i].gamma != 0.0)
+        if (so_y_terms(p[i].so) && p[i].gamma != 0.0)
             return fail(SSGP_EINVAL, "instance %d: y-dependent SO forms are not supported in batched mode", i);
         spans[i] = {offsets[i], offsets[i] + 3LL * nx[i] * ny[i]};
     }

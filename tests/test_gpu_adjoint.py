@@ -48,10 +48,12 @@ def start(dim, nx, ny, dx, seed):
     return base * (1 + W.random_state(base.shape, seed, 0.05))
 
 
-@pytest.mark.parametrize("dim,nx,ny", [(2, 40, 33), (2, 130, 70), (2, 300, 17), (1, 200, 1), (1, 600, 1)])
-def test_adjoint_steps_match_oracle(dim, nx, ny):
+@pytest.mark.parametrize("dim,nx,ny,so", [(2, 40, 33, api.SO_PX_SX), (2, 130, 70, api.SO_PX_SX),
+                                          (2, 300, 17, api.SO_PX_SX), (1, 200, 1, api.SO_PX_SX),
+                                          (1, 600, 1, api.SO_PX_SX), (2, 64, 40, api.SO_ERD)])
+def test_adjoint_steps_match_oracle(dim, nx, ny, so):
     dx = 0.3 if dim == 2 else 0.1
-    base = base_cfg(dim, nx, ny, dx)
+    base = base_cfg(dim, nx, ny, dx, so=so)
     sched = [0.05, 0.25, 0.12]
     sps, steps = 3, 9
     psi0 = start(dim, nx, ny, dx, 1)

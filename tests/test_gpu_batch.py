@@ -26,12 +26,13 @@ def rel(a, b):
 
 
 # (ny, nx, dx, c0, c2, gamma, omega, so): ragged shapes with tails in both
-# directions, single rows and columns, the largest size, and one instance on
-# the fixed-magnetisation RENORM rule (Omega = 0, no SO)
+# directions, single rows and columns, the largest size, one instance with the
+# equal-mixture SO form (x derivatives only), and one on the fixed-
+# magnetisation RENORM rule (Omega = 0, no SO)
 RAGGED = [
     (33, 40, 0.30, 3.0, -0.7, 0.6, 0.25, api.SO_PX_SX),
     (64, 64, 0.25, 1.0, 0.3, 0.0, 0.10, api.SO_NONE),
-    (70, 130, 0.22, 4.0, -0.2, 0.9, 0.05, api.SO_PX_SX),
+    (70, 130, 0.22, 4.0, -0.2, 0.9, 0.05, api.SO_ERD),
     (200, 17, 0.20, 2.0, 0.1, 0.4, 0.30, api.SO_PX_SX),
     (48, 512, 0.10, 2.5, -0.4, 0.7, 0.20, api.SO_PX_SX),
     (512, 24, 0.10, 1.5, 0.2, 0.3, 0.15, api.SO_PX_SX),
