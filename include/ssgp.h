@@ -163,7 +163,8 @@ long long ssgp_get_step_index(ssgp_grid g);
  * RENORM after every step; the state is normalised on return.  On 2D grids
  * runs of steps are enqueued as HIP graph replays (captured once per run
  * length on a library-owned stream, launched on the grid's stream; kernel-
- * timed steps and the y-derivative SO forms are launched one by one); the
+ * timed steps and the y-derivative SO forms (Rashba, Dresselhaus) are
+ * launched one by one); the
  * stream ordering is the same either way. */
 int ssgp_step_imag(ssgp_grid g, int nsteps);
 
@@ -189,7 +190,8 @@ int ssgp_observables(ssgp_grid g, ssgp_obs *out);
  * pointwise HERM o CALCNU map recomputed from the step input.  The
  * derivative of L with respect to each step's Omega is accumulated on the
  * device per schedule segment (read with ssgp_omega_grad).  Moves the step
- * index back by nsteps. */
+ * index back by nsteps.  EINVAL for the SO forms with y derivatives (Rashba,
+ * Dresselhaus); ESTATE under the unitary-SO scheme or real-time RENORM. */
 int ssgp_step_real_adjoint(ssgp_grid g, const void *states_dev, void *lambda_dev, int nsteps);
 
 /* Copies the accumulated dL/dOmega per segment (nseg values, one value when
@@ -204,7 +206,8 @@ int ssgp_destroy(ssgp_grid g);
  * is nx[i] x ny[i] points (1 <= nx, ny <= 512) with spacing dx[i] in both
  * directions, its state at pool_dev + offsets[i] elements (3*ny*nx
  * elements, the layout above; the states must not overlap), parameters p[i]
- * (every SO form without a y derivative: none or gamma p_x Sigma_x).  n is
+ * (every SO form without a y derivative: none, gamma p_x Sigma_x or the
+ * equal mixture of Rashba and Dresselhaus couplings).  n is
  * at most 65536.  The arrays are copied; the pool stays owned by the caller
  * and must outlive the batch.  Creation synchronises the stream. */
 int ssgp_create_batch(int n, const int *nx, const int *ny, const double *dx,
