@@ -163,9 +163,10 @@ long long ssgp_get_step_index(ssgp_grid g);
  * RENORM after every step; the state is normalised on return.  On 2D grids
  * runs of steps are enqueued as HIP graph replays (captured once per run
  * length on a library-owned stream, launched on the grid's stream; kernel-
- * timed steps and the y-derivative SO forms (Rashba, Dresselhaus) are
- * launched one by one); the
- * stream ordering is the same either way. */
+ * timed steps are launched one by one); the stream ordering is the same
+ * either way.  The y-derivative SO forms (Rashba, Dresselhaus) take a
+ * 3*nx*ny state-sized device scratch buffer, allocated at the first such
+ * call and held until ssgp_destroy. */
 int ssgp_step_imag(ssgp_grid g, int nsteps);
 
 /* nsteps >= 0 full real-time steps on the bound state, in place (graph

@@ -686,13 +686,16 @@ static int step_graph(ssgp_grid g, int mode, int k, bool renorm_first, double om
 
 // n in-place 2D steps of g->psi at a fixed Omega.  Runs of steps go out as
 // graph replays (runs of 2^i <= 64 steps), except steps whose kernels are
-// timed and the y-derivative SO forms (their extra pass copies the state),
-// which are launched one by one.  Imaginary time (and real time with
+// timed, which are launched one by one.  Imaginary time (and real time with
 // renorm_real): every step but (unless renorm_first) the first applies the
 // previous step's RENORM.
 template <typename R> static int run_steps(ssgp_grid g, int mode, int n, double omega, bool renorm_first) {
     if (!g->renorms(mode)) renorm_first = false;
-    const bool graphable = g->dim == 2 && !(so_y_terms(g->p.so) && g->p.gamma != 0.0);
+    const bool graphable = g->dim == 2;
+    // the y-derivative SO forms' pointwise pass writes a scratch copy:
+    // allocate it before any capture
+    if (so_y_terms(g->p.so) && g->p.gamma != 0.0)
+        SSGP_TRY(g->scratch.ensure((size_t)3 * plane_of(*g) * sizeof(cx<R>)));
     int s = 0;
     while (s < n) {
         const bool timing = g->prof_every > 0 && g->prof_used < g->prof_cap;

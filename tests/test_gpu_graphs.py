@@ -111,3 +111,27 @@ def test_sampled_timing_mixes_graphs_and_single_steps(every, capacity):
     assert p["steps"] == min(capacity, len(range(0, 57, every)))
     ge.close()
     gg.close()
+
+
+
+@pytest.mark.parametrize("imag", [False, True], ids=["real", "imag"])
+def test_y_derivative_so_runs_as_graphs(imag):
+    """The Rashba form (its pointwise pass writes a scratch copy that the
+    x-pass reads) replayed as graphs: bitwise equal to one-by-one launches,
+    and against the oracle."""
+    nx, ny, dx = 80, 56, 0.25
+    prm = dict(c0=2.0, c2=-0.3, gamma=0.5, omega=0.1, dt=2e-3, so=api.SO_RASHBA)
+    (ge, te), (gg, tg) = pair(nx, ny, dx, **prm)
+    base = W.gaussian(2, nx, ny, dx, dx, phases=(0.3, 1.1, 2.0), width=1.5)
+    psi0 = base * (1 + W.random_state(base.shape, 4, 0.05))
+    for n in (13, 64, 7):
+        (ge.step_imag if imag else ge.step_real)(n)
+        (gg.step_imag if imag else gg.step_real)(n)
+        _ = (tg.abs() ** 2).sum().item()
+        assert same(te, tg), n
+    got = tg.cpu().numpy()
+    ge.close()
+    gg.close()
+    cfg = oracle.Cfg(dim=2, nx=nx, ny=ny, dx=dx, dy=dx, imag=imag, **prm)
+    want = oracle.step(cfg, psi0, 84)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-10

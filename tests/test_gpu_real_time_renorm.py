@@ -1,8 +1,7 @@
 """RENORM after every real-time step (opt-in, ssgp_set_renorm_real) on the
 GPU against the oracle's definition (oracle.step_real_renorm: each step, then
 the rule of Eqs. (DJ)/(DJ2)): relative L2 <= 1e-10 in FP64 for the paper's
-scheme (graph-replayed runs, and the y-derivative SO path launched one step
-at a time) and the unitary-SO scheme, in 2D and 1D, across Omega-schedule
+scheme (graph-replayed runs, the y-derivative SO path included) and the unitary-SO scheme, in 2D and 1D, across Omega-schedule
 segments; graph replays bitwise equal to one-by-one launches; switching it
 off; and the refusals."""
 import numpy as np
