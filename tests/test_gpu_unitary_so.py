@@ -20,7 +20,7 @@ from paper_2009_13507_amd._lib import SSGPError  # noqa: E402
 
 DEV = "cuda:0"
 PRM = dict(c0=2.0, c2=-0.3, gamma=0.7, omega=0.15, so=api.SO_PX_SX)
-SHAPES = [(72, 40), (256, 20), (300, 9), (512, 9), (700, 6), (1024, 5), (1500, 3), (2048, 3)]
+SHAPES = [(72, 40), (256, 20), (300, 9), (512, 9), (700, 6), (1024, 5), (1500, 3), (2048, 3), (1, 1), (3, 2)]
 
 
 def start(nx, ny, dx, seed):
@@ -165,7 +165,7 @@ def test_unitary_so_full_size_against_oracle():
 
 @pytest.mark.parametrize("imag", [False, True], ids=["real", "imag"])
 @pytest.mark.parametrize("so", [api.SO_PX_SX, api.SO_PX_SY, api.SO_PX_SZ], ids=["Sx", "Sy", "Sz"])
-@pytest.mark.parametrize("nx", [100, 512, 640, 2048])
+@pytest.mark.parametrize("nx", [100, 512, 640, 2048, 1, 33])
 def test_unitary_so_1d_matches_oracle(nx, so, imag):
     dx, dt = 0.05, 5e-4
     base = W.gaussian(1, nx, 1, dx, dx, phases=(0.3, 1.1, 2.0), width=0.15 * nx * dx)
