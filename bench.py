@@ -17,8 +17,8 @@ Prints one JSON line:
              same workload (first steps from the same initial state).
 Beside them: the forward+adjoint cost ratio, the batched-vs-serial
 comparison, the imaginary-time workloads, the same 1024^2 workload under the
-opt-in unitary-SO scheme (unitary_so) and in complex64 (complex64_step, with
-its difference from complex128).
+opt-in unitary-SO scheme (unitary_so), with the Rashba coupling (rashba_step)
+and in complex64 (complex64_step, with its difference from complex128).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -184,6 +184,36 @@ def unitary_so(steps: int = 1000, warmup: int = 50, every: int = 7):
             "norm_change": n1 - n0}
 
 
+def rashba_step(steps: int = 1000, warmup: int = 50, every: int = 7):
+    """The 1024^2 real-time workload with the Rashba coupling (y derivatives
+    in the SO term: a pointwise pass into a scratch copy, then the x-pass
+    variant that reads rows iy +- 1, then the y-pass): step rate and the
+    x-pass and y-pass kernel times (HIP events on every `every`-th step)."""
+    import torch
+
+    from paper_2009_13507_amd import api
+    from paper_2009_13507_amd import workloads as W
+
+    w = W.W2D_REAL
+    state = torch.from_numpy(W.initial_2d_real(w)).to("cuda:0")
+    g = api.Grid(state, w.dx, w.dy)
+    g.set_params(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, dt=w.dt, so=api.SO_RASHBA)
+    g.step_real(warmup)
+    g.profile(every, capacity=steps // every + 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step_real(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = g.profile_read()
+    g.profile(0)
+    g.close()
+    npts = w.nx * w.ny
+    return {"workload": w.name + " (Rashba coupling)", "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "pt_steps_per_s": npts * steps / el,
+            "kernels_ms": {"xpass": prof["x_ms"], "ypass": prof["y_ms"], "profiled_steps": prof["steps"]}}
+
+
 def complex64_step(steps: int = 1000, warmup: int = 50):
     """The 1024^2 real-time workload in complex64 (FP32 storage and
     arithmetic): step rate, and the relative L2 difference from the same
@@ -285,7 +315,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint cost ratio")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-serial comparison")
-    ap.add_argument("--no-uso", action="store_true", help="skip the unitary-SO scheme figures")
+    ap.add_argument("--no-uso", action="store_true", help="skip the unitary-SO scheme and Rashba-coupling figures")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run torch copies of the state size (counter calibration)")
     args = ap.parse_args()
@@ -379,6 +409,7 @@ def main():
         line["adjoint_cost_ratio"] = adjoint_ratio()
     if not args.no_uso and args.dtype == "f64":
         line["unitary_so"] = unitary_so()
+        line["rashba_step"] = rashba_step()
     if not args.no_batch and args.dtype == "f64":
         line["complex64_step"] = complex64_step()
     if not args.no_batch:
