@@ -82,7 +82,9 @@ class _Propagate(torch.autograd.Function):
                 g.step_real_seq(seg[0], seg[1:n], n - 1)
             g.step_index = n0 + n
             g.step_real_adjoint(seg[:n], lam, n)
-        domega = torch.tensor(g.omega_grad(reset=True), dtype=torch.float64, device=grad_out.device)
+        (omega,) = ctx.saved_tensors
+        # the gradient lives where (and in the dtype that) the caller's Omega does
+        domega = torch.tensor(g.omega_grad(reset=True), dtype=omega.dtype, device=omega.device)
         ctx.checkpoints = None
         return lam, domega, None
 

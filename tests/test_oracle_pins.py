@@ -528,3 +528,72 @@ def test_ground_state_energy_matches_table4(ora, name, c0, c2, m, rn, wts, print
     o = ora.observables(cfg, psi)
     assert abs(o["E"] - printed) < 1e-4, (name, o["E"])
     assert abs(o["M"] - m) < 1e-12
+
+
+# ------------------------------------------------------------- rms sizes
+def _displaced_gaussians(dim, n, h, centre, widths, weights, phases=(0.4, 1.3, 2.9)):
+    """psi_j = sqrt(w_j) e^{i theta_j} exp(-(x-x0)^2/(2 sx_j^2) - (y-y0)^2/(2 sy_j^2))
+    on the half-open grid x_i = -n h / 2 + i h (not normalised)."""
+    x = W.coords(n, h)
+    comps = []
+    for (sx, sy), w, th in zip(widths, weights, phases):
+        gx = np.exp(-(x - centre[0]) ** 2 / (2 * sx ** 2))
+        if dim == 1:
+            g = gx
+        else:
+            gy = np.exp(-(W.coords(n, h) - centre[1]) ** 2 / (2 * sy ** 2))
+            g = gy[:, None] * gx[None, :]
+        comps.append(np.sqrt(w) * np.exp(1j * th) * g)
+    return np.stack(comps).astype(np.complex128)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_rms_sizes_are_gaussian_second_moments(ora, dim):
+    """rms_j = sqrt(sum r^2 rho_j / sum rho_j) about the origin of the grid
+    (Sec. 3 output quantities, Table 1's LENGTH/RADIUS): for a Gaussian density
+    rho_j ~ exp(-(x-x0)^2/sx^2 - (y-y0)^2/sy^2) the continuum moment is
+    <x^2 + y^2> = x0^2 + sx^2/2 + y0^2 + sy^2/2, and on a uniform grid with
+    spacing far below the width the rectangle-rule sums equal it to rounding
+    (Poisson summation: the error is of order exp(-pi^2 s^2 / h^2)).  The
+    components have unequal weights, widths and anisotropies, and the centre is
+    off the origin and off the grid points, so a wrong centre, a division by
+    the total instead of the component norm, a dropped y^2 or a grid shifted
+    by half a cell all fail."""
+    n, h = 256, 0.1
+    centre = (0.83, -0.61)
+    widths = [(0.9, 1.2), (1.1, 0.7), (0.6, 1.0)]
+    weights = (0.5, 0.2, 0.3)
+    psi = _displaced_gaussians(dim, n, h, centre, widths, weights)
+    cfg = ora.Cfg(dim=dim, nx=n, ny=n if dim == 2 else 1, dx=h, dy=h)
+    obs = ora.observables(cfg, psi)
+    mom, mass = [], []
+    for (sx, sy), w in zip(widths, weights):
+        if dim == 1:
+            mom.append(centre[0] ** 2 + sx ** 2 / 2)
+            mass.append(w * sx * np.sqrt(np.pi))          # integral of w exp(-x^2/sx^2)
+        else:
+            mom.append(centre[0] ** 2 + sx ** 2 / 2 + centre[1] ** 2 + sy ** 2 / 2)
+            mass.append(w * np.pi * sx * sy)
+    for j, key in enumerate(("rms+1", "rms0", "rms-1")):
+        assert abs(obs[key] - np.sqrt(mom[j])) < 1e-12, (key, obs[key], np.sqrt(mom[j]))
+    tot = np.sqrt(np.dot(mass, mom) / np.sum(mass))
+    assert abs(obs["rms"] - tot) < 1e-12
+    # the component norms the rms sizes are divided by: N_j = dA sum rho_j
+
+    for j, key in enumerate(("N+1", "N0", "N-1")):
+        assert abs(obs[key] - mass[j]) < 1e-12 * max(1.0, mass[j]), (key, obs[key], mass[j])
+    # rms sizes do not depend on the overall normalisation or the phases
+    obs2 = ora.observables(cfg, 3.7 * np.exp(0.9j) * psi)
+    for key in ("rms+1", "rms0", "rms-1", "rms"):
+        assert abs(obs2[key] - obs[key]) < 1e-13
+
+
+
+def test_rms_of_empty_component_is_zero(ora):
+    """A component with no atoms has rms 0 (guard N_j = 0); the total uses rho."""
+    n, h = 128, 0.1
+    psi = _displaced_gaussians(1, n, h, (0.0, 0.0), [(1.0, 1.0)] * 3, (0.5, 0.5, 0.0))
+    cfg = ora.Cfg(dim=1, nx=n, dx=h)
+    obs = ora.observables(cfg, psi)
+    assert obs["rms-1"] == 0.0
+    assert abs(obs["rms+1"] - np.sqrt(0.5)) < 1e-12 and abs(obs["rms"] - np.sqrt(0.5)) < 1e-12
