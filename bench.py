@@ -8,13 +8,18 @@ one full SS-CN time step (CALCNU, HERM, SO, LUX, LUY) of the whole grid.
 
 Prints one JSON line:
   value      grid-point-steps per second over the timed steps (state resident
-             in HBM when the timed region starts);
+             in HBM when the timed region starts; the observables are recorded
+             into a device-side log inside the timed region and read after it;
+             the warm-up runs the timed schedule once, so every graph the timed
+             steps replay is captured beforehand);
   roofline   the dominant kernel's algorithmic bytes per launch over its mean
              duration (HIP start/stop events attached to its launches on the
-             library's stream, about every 50th step of the timed region) against
-             the 8 TB/s HBM peak;
+             library's stream, every 7th step of a window of at least 50
+             profiled steps after the timed one) against the 8 TB/s HBM peak;
+  copy_ceiling  a device copy of the state (read + write) timed alike;
   cpu_baseline  the CPU oracle on the host cores, on a bounded sample of the
-             same workload (first steps from the same initial state).
+             same workload (first steps from the same initial state), with all
+             threads and with one, and the CPU model.
 Beside them: the forward+adjoint cost ratio, the batched-vs-serial
 comparison, the imaginary-time workloads, the same 1024^2 workload under the
 opt-in unitary-SO scheme (unitary_so), with the Rashba coupling (rashba_step)
@@ -62,21 +67,68 @@ def measured_traffic(kernel: str, npts: int):
     return t.get("bytes_per_launch", {}).get(kernel)
 
 
-def cpu_baseline(w, psi0, seconds: float):
-    import oracle
-    cfg = oracle.Cfg(dim=2, nx=w.nx, ny=w.ny, dx=w.dx, dy=w.dy, c0=w.c0, c2=w.c2, gamma=w.gamma,
-                     omega=w.omega, dt=w.dt, imag=False, so=w.so)
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(oracle, cfg, psi0, seconds: float, max_steps: int):
     psi = psi0
     steps = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds and steps < 400:
-        psi = oracle.step(cfg, psi, 2)
-        steps += 2
-    el = time.perf_counter() - t0
-    return {"value": w.nx * w.ny * steps / el, "unit": "grid-point-steps/s", "cores": oracle.num_threads(),
+    while time.perf_counter() - t0 < seconds and steps < max_steps:
+        psi = oracle.step(cfg, psi, 1)
+        steps += 1
+    return steps, time.perf_counter() - t0
+
+
+def cpu_baseline(w, psi0, seconds: float):
+    """The oracle (plain FP64 C, OpenMP over grid lines) on the host cores:
+    the first steps of the same workload from the same initial state, with all
+    the threads the process may use and with one thread."""
+    import oracle
+    cfg = oracle.Cfg(dim=2, nx=w.nx, ny=w.ny, dx=w.dx, dy=w.dy, c0=w.c0, c2=w.c2, gamma=w.gamma,
+                     omega=w.omega, dt=w.dt, imag=False, so=w.so)
+    nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    oracle.set_num_threads(nthreads)
+    used = oracle.num_threads()
+    steps, el = _oracle_rate(oracle, cfg, psi0, seconds, 400)
+    oracle.set_num_threads(1)
+    steps1, el1 = _oracle_rate(oracle, cfg, psi0, seconds / 2, 50)
+    oracle.set_num_threads(used)
+    npts = w.nx * w.ny
+    return {"value": npts * steps / el, "unit": "grid-point-steps/s", "cores": used,
             "kind": "oracle",
             "sample": f"first {steps} steps of the 1024^2 real-time workload from its initial state "
-                      f"({el:.1f} s, FP64, OpenMP over grid lines)"}
+                      f"({el:.1f} s, FP64, OpenMP over grid lines, {used} threads)",
+            "single_thread": {"value": npts * steps1 / el1, "steps": steps1, "seconds": el1},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def copy_ceiling(t, reps: int = 50):
+    """A plain device copy of a state-sized buffer (read + write), timed with
+    HIP events over reps copies: the practical floor of one pass."""
+    import torch
+    a = t.clone()
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    nbytes = 2 * a.numel() * a.element_size()
+    return {"bytes_per_copy": nbytes, "us": us, "GBs": nbytes / (us * 1e-6) / 1e9,
+            "frac_of_peak": nbytes / (us * 1e-6) / (HBM_PEAK_GBS * 1e9)}
 
 
 def adjoint_ratio(reps: int = 2):
@@ -309,8 +361,9 @@ def main():
     ap.add_argument("--obs-every", type=int, default=100)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--profile-every", type=int, default=0,
-                    help="time the kernels of every n-th step (default: the largest n <= 50 coprime with "
-                         "--obs-every, so that every position between two observable reads is sampled alike)")
+                    help="in the kernel-timing window after the timed one, time the kernels of every n-th "
+                         "step (default 7)")
+    ap.add_argument("--profile-steps", type=int, default=50, help="profiled steps (at least 50)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint cost ratio")
@@ -339,29 +392,45 @@ def main():
     g = api.Grid(state, w.dx, w.dy)
     g.set_params(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, dt=w.dt, so=w.so)
 
-    # warm-up on the same buffers, then restart from the initial state
+    K = args.steps
+    nobs = K // args.obs_every + 1
+    g.obs_log_reserve(nobs)
+
+    def run(k):
+        """k steps with the observables of the state after steps 0, obs_every,
+        2 obs_every, ... recorded on the device (no host synchronisation)."""
+        g.obs_record()
+        done = 0
+        while done < k:
+            n = min(args.obs_every - done % args.obs_every, k - done)
+            g.step_real(n)
+            done += n
+            if done % args.obs_every == 0:
+                g.obs_record()
+
+    # warm-up: W steps, then the timed schedule once (so that every graph
+    # length it replays is captured beforehand); then back to the initial state
     g.step_real(args.warmup)
-    g.observables()
+    g.obs_log_reserve(nobs)
+    run(K)
+    g.obs_log_reserve(nobs)
     state.copy_(init)
+    g.step_index = 0
     torch.cuda.synchronize()
 
-    K = args.steps
-    obs_log = []
-    every = args.profile_every
-    if every <= 0:
-        every = next(p for p in range(50, 0, -1) if math.gcd(p, args.obs_every) == 1)
-    g.profile(every, capacity=K // every + 2)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    obs_log.append(g.observables())
-    done = 0
-    while done < K:
-        n = min(args.obs_every, K - done)
-        g.step_real(n)
-        done += n
-        obs_log.append(g.observables())
+    run(K)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    obs_log = g.obs_log_read()
+
+    # kernel times: a separate window after the timed one, HIP start/stop
+    # events attached to the x-pass and y-pass launches of every 7th step
+    # (the others replayed as graphs), at least 50 profiled steps
+    every = args.profile_every if args.profile_every > 0 else 7
+    nprof = max(50, args.profile_steps)
+    g.profile(every, capacity=nprof + 2)
+    g.step_real(every * nprof)
     prof = g.profile_read()
     g.profile(0)
 
@@ -373,13 +442,7 @@ def main():
     mean_ms = max(prof["x_ms"], prof["y_ms"])
     achieved = per_launch / (mean_ms * 1e-3) / 1e9
     traffic = measured_traffic(kern, npts)
-
-    if args.copy_probe:
-        a = init.clone()
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
+    ceiling = copy_ceiling(init)
 
     line = {
         "metric": "2D SS-CN grid-point-steps/s, 1024^2 FP64, % of HBM peak; fwd+adjoint cost ratio",
@@ -399,10 +462,13 @@ def main():
                    "omega": w.omega, "observables_every": args.obs_every,
                    "initial_state": "256^2 imaginary-time ground state, linearly interpolated"},
         "hbm_frac_step_algorithmic": 2 * bpp * value / (HBM_PEAK_GBS * 1e9),
-        "kernels_ms": {"xpass": prof["x_ms"], "ypass": prof["y_ms"], "profiled_steps": prof["steps"]},
+        "kernels_ms": {"xpass": prof["x_ms"], "ypass": prof["y_ms"], "profiled_steps": prof["steps"],
+                       "profile_every": every},
         "roofline": {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": per_launch},
+        "copy_ceiling": dict(ceiling, kernel_frac_of_copy=achieved / ceiling["GBs"]),
+        "observable_samples": len(obs_log),
         "final_observables": {k: obs_log[-1][k] for k in ("N", "M", "E", "rms")},
     }
     if not args.no_adjoint and args.dtype == "f64":

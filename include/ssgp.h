@@ -30,8 +30,9 @@
  * and frees it in ssgp_destroy / ssgp_destroy_batch.
  *
  * Streams.  Every call is enqueued on the HIP stream given at creation and
- * returns without waiting, except ssgp_observables, ssgp_batch_observables
- * and ssgp_omega_grad, which synchronise that stream.
+ * returns without waiting, except ssgp_observables, ssgp_obs_log_reserve,
+ * ssgp_obs_log_read, ssgp_batch_observables and ssgp_omega_grad, which
+ * synchronise that stream.
  *
  * Errors.  Every entry point returns SSGP_OK (0) or a negative code and never
  * throws; ssgp_last_error() returns the message of the calling thread's last
@@ -179,8 +180,26 @@ int ssgp_step_real(ssgp_grid g, int nsteps);
 int ssgp_step_real_seq(ssgp_grid g, const void *src_dev, void *dst_dev, int nsteps);
 
 /* Observables of the bound state; synchronises the stream.  Returns
- * SSGP_ENONFINITE (with *out filled) when the norm is NaN or Inf. */
+ * SSGP_ENONFINITE (with *out filled) when the norm is NaN or Inf.  The Rabi
+ * part of E (Eq. (5)) uses params.omega after ssgp_set_params, and after a
+ * step call the Omega of the last step taken (imaginary time: params.omega;
+ * real time: the schedule's value for that step's index). */
 int ssgp_observables(ssgp_grid g, ssgp_obs *out);
+
+/* Observables sampled inside a stepping loop without a host synchronisation
+ * (the same sums as ssgp_observables, Eqs. (4)-(5), Omega rule as there).
+ * ssgp_obs_log_reserve synchronises the stream, allocates a device log of
+ * capacity samples (12 doubles each; capacity = 0 keeps the buffer) and
+ * empties it.  ssgp_obs_record enqueues the observables of the bound state
+ * into the next free sample on the grid's stream and returns at once; ESTATE
+ * when the log is full or no parameters are set.  ssgp_obs_log_read
+ * synchronises the stream, writes the first min(max, recorded) samples in
+ * record order to out and the number recorded to *count (the log is kept;
+ * reserve again to empty it); ENONFINITE when a written sample holds NaN or
+ * Inf. */
+int ssgp_obs_log_reserve(ssgp_grid g, int capacity);
+int ssgp_obs_record(ssgp_grid g);
+int ssgp_obs_log_read(ssgp_grid g, ssgp_obs *out, int max, int *count);
 
 /* Adjoint of real-time steps (reverse-mode derivative in the convention
  * grad = dL/dRe(psi) + i dL/dIm(psi)).  states_dev holds the nsteps step

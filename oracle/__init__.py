@@ -110,6 +110,8 @@ def lib():
         L.ora_step_adjoint.restype = ctypes.c_int
         L.ora_num_threads.argtypes = []
         L.ora_num_threads.restype = ctypes.c_int
+        L.ora_set_num_threads.argtypes = [ctypes.c_int]
+        L.ora_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -211,6 +213,11 @@ def step_adjoint(cfg: Cfg, psi_n, lam):
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (timing only)."""
+    lib().ora_set_num_threads(int(n))
 
 
 # ------------------------------------------- unitary-SO scheme (opt-in) --

@@ -82,6 +82,18 @@ int ora_num_threads(void)
 #endif
 }
 
+/* threads of the parallel loops that follow (for timing; the steps and the
+ * norms do not depend on it, the adjoint's Omega derivative only through the
+ * order of its sum) */
+void ora_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------- CALCNU */
 /* Diagonal part of Eqs. (1)-(2): phi_{+-1} = V + c0 rho + c2 (rho_{+-1} - rho_{-+1} + rho_0),
  * phi_0 = V + c0 rho + c2 (rho_{+1} + rho_{-1}), V = (x^2 + kappa^2 y^2)/2 (Sec. 2). */

@@ -73,6 +73,9 @@ def load():
         "ssgp_step_real": ([G, ci], ci),
         "ssgp_step_real_seq": ([G, vp, vp, ci], ci),
         "ssgp_observables": ([G, ctypes.POINTER(Obs)], ci),
+        "ssgp_obs_log_reserve": ([G, ci], ci),
+        "ssgp_obs_record": ([G], ci),
+        "ssgp_obs_log_read": ([G, ctypes.POINTER(Obs), ci, ctypes.POINTER(ci)], ci),
         "ssgp_step_real_adjoint": ([G, vp, vp, ci], ci),
         "ssgp_omega_grad": ([G, ctypes.POINTER(cd), ci, ci], ci),
         "ssgp_destroy": ([G], ci),

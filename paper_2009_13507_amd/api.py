@@ -156,6 +156,25 @@ class Grid:
             raise SSGPError(rc, self._lib.ssgp_last_error().decode())
         return o.as_dict()
 
+    def obs_log_reserve(self, capacity: int):
+        """Device-side log of up to ``capacity`` observable samples (cleared)."""
+        check(self._lib.ssgp_obs_log_reserve(self._h, int(capacity)))
+
+    def obs_record(self):
+        """Appends the observables of the current state to the device log,
+        asynchronously (no host synchronisation)."""
+        check(self._lib.ssgp_obs_record(self._h))
+
+    def obs_log_read(self) -> list:
+        """Synchronises and returns the logged samples, oldest first."""
+        count = ctypes.c_int(0)
+        check(self._lib.ssgp_obs_log_read(self._h, None, 0, ctypes.byref(count)))
+        out = (Obs * max(1, count.value))()
+        rc = self._lib.ssgp_obs_log_read(self._h, out, count.value, ctypes.byref(count))
+        if rc != _lib.OK:
+            raise SSGPError(rc, self._lib.ssgp_last_error().decode())
+        return [out[k].as_dict() for k in range(count.value)]
+
 
 class Batch:
     """n independent 2D grids in one device pool, stepped together in

@@ -295,7 +295,13 @@ struct GridCore {
     std::vector<double> omega_sched;
     int steps_per_seg = 1;
     long long step_index = 0;
+    // Omega of the Rabi energy in the observables: params.omega after
+    // ssgp_set_params, then the Omega of the last step taken
+    double obs_omega = 0.0;
     DevBuf partials, renorm, obs_partials, obs_out, scratch, omega_acc, adj_partials;
+    // device-side observables log: OBS_NQ sums per sample
+    DevBuf obs_log;
+    int obs_log_cap = 0, obs_log_used = 0;
     int built_mode_mask = 0;
     // kernel timing: start/stop events of the x-pass and y-pass kernels of
     // every prof_every-th step (event pairs [x0, x1, y0, y1] per profiled step)
@@ -760,6 +766,7 @@ template <typename R> static int final_renorm(ssgp_grid g) {
 
 template <typename R> static int step_imag_t(ssgp_grid g, int nsteps) {
     SSGP_TRY(build_tables<R>(g, MODE_IMAG));
+    if (nsteps > 0) g->obs_omega = g->p.omega;
     if (g->dim == 1) return launch_1d<R>(g, MODE_IMAG, g->psi, nsteps, g->p.omega);
     SSGP_TRY(run_steps<R>(g, MODE_IMAG, nsteps, g->p.omega, false));
     if (nsteps > 0) SSGP_TRY(final_renorm<R>(g));
@@ -768,6 +775,7 @@ template <typename R> static int step_imag_t(ssgp_grid g, int nsteps) {
 
 template <typename R> static int step_real_t(ssgp_grid g, const void *src, void *dst, int nsteps, bool seq) {
     SSGP_TRY(build_tables<R>(g, MODE_REAL));
+    if (nsteps > 0) g->obs_omega = omega_at(*g, g->step_index + nsteps - 1);
     const size_t state_elems = (size_t)3 * plane_of(*g);
     if (g->dim == 1) {
         // 1D: the whole run stays in LDS; split launches where Omega changes
@@ -901,6 +909,7 @@ extern "C" int ssgp_set_params(ssgp_grid g, const ssgp_params *p) {
     g->clear_graphs();  // the graphs hold the model constants
     g->p = *p;
     g->have_params = true;
+    g->obs_omega = p->omega;
     return SSGP_OK;
 }
 
@@ -975,7 +984,10 @@ extern "C" int ssgp_step_real_seq(ssgp_grid g, const void *src, void *dst, int n
                                  : step_real_t<float>(g, src, dst, nsteps, true);
 }
 
-template <typename R> static int observables_t(ssgp_grid g, const void *psi, ssgp_obs *out) {
+// Launches the observables pass over psi; the 12 fixed-order sums go to
+// out_dev (device memory).  E_rabi takes the Omega of the last step taken
+// (GridCore::obs_omega).
+template <typename R> static int observables_launch(ssgp_grid g, const void *psi, double *out_dev) {
     ObsArgs<R> a{};
     a.psi = static_cast<const cx<R> *>(psi);
     a.dim = g->dim;
@@ -989,7 +1001,7 @@ template <typename R> static int observables_t(ssgp_grid g, const void *psi, ssg
     a.kappa2 = g->p.kappa * g->p.kappa;
     a.c0 = g->p.c0;
     a.c2 = g->p.c2;
-    a.om_t = omega_at(*g, g->step_index) / std::sqrt(2.0);
+    a.om_t = g->obs_omega / std::sqrt(2.0);
     const SOForm f = so_form(g->p.so, g->p.gamma);
     for (int q = 0; q < 9; ++q) {
         a.hx[q] = cx<double>{f.hx[q].real(), f.hx[q].imag()};
@@ -1000,11 +1012,13 @@ template <typename R> static int observables_t(ssgp_grid g, const void *psi, ssg
     a.partials = g->obs_partials.as<double>();
     const int nb = (int)std::min<long long>((a.plane + 255) / 256, 1024);
     LAUNCH_TRY(launch_obs<R>(lc(*g), a, nb));
-    LAUNCH_TRY(launch_obs_finalize(lc(*g), g->obs_partials.as<double>(), nb, g->obs_out.as<double>()));
-    double h[OBS_NQ];
-    HIP_TRY(hipMemcpyAsync(h, g->obs_out.p, sizeof h, hipMemcpyDeviceToHost, g->stream));
-    HIP_TRY(hipStreamSynchronize(g->stream));
-    const double dA = darea(*g);
+    LAUNCH_TRY(launch_obs_finalize(lc(*g), g->obs_partials.as<double>(), nb, out_dev));
+    return SSGP_OK;
+}
+
+// ssgp_obs from the 12 sums of the observables pass.
+static int obs_from_sums(const GridCore &g, const double *h, ssgp_obs *out) {
+    const double dA = darea(g);
     ssgp_obs o{};
     for (int j = 0; j < 3; ++j) o.N[j] = h[j] * dA;
     o.Ntot = o.N[0] + o.N[1] + o.N[2];
@@ -1019,10 +1033,56 @@ template <typename R> static int observables_t(ssgp_grid g, const void *psi, ssg
     return SSGP_OK;
 }
 
+template <typename R> static int observables_t(ssgp_grid g, const void *psi, ssgp_obs *out) {
+    SSGP_TRY(observables_launch<R>(g, psi, g->obs_out.as<double>()));
+    double h[OBS_NQ];
+    HIP_TRY(hipMemcpyAsync(h, g->obs_out.p, sizeof h, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return obs_from_sums(*g, h, out);
+}
+
 extern "C" int ssgp_observables(ssgp_grid g, ssgp_obs *out) {
     if (!g || !out) return fail(SSGP_EINVAL, "NULL argument");
     if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
     return g->dtype == SSGP_C128 ? observables_t<double>(g, g->psi, out) : observables_t<float>(g, g->psi, out);
+}
+
+extern "C" int ssgp_obs_log_reserve(ssgp_grid g, int capacity) {
+    if (!g) return fail(SSGP_EINVAL, "grid is NULL");
+    if (capacity < 0) return fail(SSGP_EINVAL, "capacity < 0");
+    HIP_TRY(hipStreamSynchronize(g->stream));  // no record into the old log in flight
+    if (capacity > 0) SSGP_TRY(g->obs_log.ensure(sizeof(double) * OBS_NQ * (size_t)capacity));
+    g->obs_log_cap = capacity;
+    g->obs_log_used = 0;
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_obs_record(ssgp_grid g) {
+    if (!g) return fail(SSGP_EINVAL, "grid is NULL");
+    if (!g->have_params) return fail(SSGP_ESTATE, "set_params first");
+    if (g->obs_log_used >= g->obs_log_cap) return fail(SSGP_ESTATE, "observables log full (%d samples)", g->obs_log_cap);
+    double *slot = g->obs_log.as<double>() + (size_t)OBS_NQ * g->obs_log_used;
+    SSGP_TRY(g->dtype == SSGP_C128 ? observables_launch<double>(g, g->psi, slot)
+                                   : observables_launch<float>(g, g->psi, slot));
+    ++g->obs_log_used;
+    return SSGP_OK;
+}
+
+extern "C" int ssgp_obs_log_read(ssgp_grid g, ssgp_obs *out, int max, int *count) {
+    if (!g || !count || (max > 0 && !out)) return fail(SSGP_EINVAL, "NULL argument");
+    if (max < 0) return fail(SSGP_EINVAL, "max < 0");
+    const int n = std::min(max, g->obs_log_used);
+    std::vector<double> h((size_t)OBS_NQ * std::max(n, 1));
+    if (n > 0)
+        HIP_TRY(hipMemcpyAsync(h.data(), g->obs_log.p, sizeof(double) * OBS_NQ * n, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    *count = g->obs_log_used;
+    int rc = SSGP_OK;
+    for (int k = 0; k < n; ++k) {
+        const int r = obs_from_sums(*g, h.data() + (size_t)OBS_NQ * k, out + k);
+        if (r != SSGP_OK && rc == SSGP_OK) rc = r;
+    }
+    return rc;
 }
 
 extern "C" int ssgp_step_real_adjoint(ssgp_grid g, const void *states_dev, void *lambda_dev, int nsteps) {

@@ -1,6 +1,7 @@
 """GPU (HIP, gfx950) against the CPU oracle, element by element, through the
 C ABI.  Tolerance (FP64): relative L2 over all components and points
-<= 1e-10; observables relative <= 1e-10 (absolute 1e-12 below 1e-2)."""
+<= 1e-10, and the largest pointwise difference relative to the largest
+|psi| <= 1e-10; observables relative <= 1e-10 (absolute 1e-12 below 1e-2)."""
 import numpy as np
 import pytest
 
@@ -18,6 +19,15 @@ DEV = "cuda:0"
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def maxrel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def close(a, b, tol=1e-10):
+    """relative L2 and relative max-abs difference both within tol"""
+    return rel(a, b) < tol and maxrel(a, b) < tol
 
 
 def ocfg(dim, nx, ny, dx, dy, imag, **p):
@@ -56,7 +66,7 @@ def test_2d_steps_match_oracle(nx, ny, imag, so):
     psi0 = start_state(2, nx, ny, dx, dy)
     got, _ = gpu_run(psi0, dx, dy, imag, 12, **p)
     ref = oracle.step(ocfg(2, nx, ny, dx, dy, imag, **p), psi0, 12)
-    assert rel(got, ref) < TOL
+    assert close(got, ref), (rel(got, ref), maxrel(got, ref))
 
 
 @pytest.mark.parametrize("nx", [512, 33, 1000, 2048, 1, 64, 65])
@@ -69,7 +79,7 @@ def test_1d_steps_match_oracle(nx, imag, so):
     psi0 = start_state(1, nx, 1, dx, dx)
     got, _ = gpu_run(psi0, dx, dx, imag, 25, **p)
     ref = oracle.step(ocfg(1, nx, 1, dx, dx, imag, **p), psi0, 25)
-    assert rel(got, ref) < TOL
+    assert close(got, ref), (rel(got, ref), maxrel(got, ref))
 
 
 @pytest.mark.parametrize("so", [api.SO_RASHBA, api.SO_DRESSELHAUS, api.SO_ERD])
@@ -80,7 +90,7 @@ def test_2d_y_derivative_so_forms(so, imag):
     psi0 = start_state(2, nx, ny, dx, dx, seed=3)
     got, _ = gpu_run(psi0, dx, dx, imag, 10, **p)
     ref = oracle.step(ocfg(2, nx, ny, dx, dx, imag, **p), psi0, 10)
-    assert rel(got, ref) < TOL
+    assert close(got, ref), (rel(got, ref), maxrel(got, ref))
 
 
 @pytest.mark.parametrize("dim", [1, 2])
@@ -90,7 +100,7 @@ def test_fixed_magnetisation_renorm(dim):
     psi0 = start_state(dim, nx, ny, dx, dx, seed=4)
     got, obs = gpu_run(psi0, dx, dx, True, 40, **p)
     ref = oracle.step(ocfg(dim, nx, ny, dx, dx, True, **p), psi0, 40)
-    assert rel(got, ref) < TOL
+    assert close(got, ref), (rel(got, ref), maxrel(got, ref))
     assert abs(obs["N"] - 1) < 1e-13 and abs(obs["M"] - 0.3) < 1e-13
 
 
@@ -122,7 +132,7 @@ def test_1d_workload_full_length():
     got, obs = gpu_run(psi0, w.dx, w.dx, True, w.steps, **p)
     cfg = ocfg(1, w.nx, 1, w.dx, w.dx, True, **p)
     ref = oracle.step(cfg, psi0, w.steps)
-    assert rel(got, ref) < TOL
+    assert close(got, ref), (rel(got, ref), maxrel(got, ref))
     oref = oracle.observables(cfg, ref)
     assert abs(obs["E"] - oref["E"]) < TOL * abs(oref["E"])
 
@@ -135,7 +145,7 @@ def test_2d_imag_workload_grid():
     got, obs = gpu_run(psi0, w.dx, w.dy, True, 300, **p)
     cfg = ocfg(2, w.nx, w.ny, w.dx, w.dy, True, **p)
     ref = oracle.step(cfg, psi0, 300)
-    assert rel(got, ref) < TOL
+    assert close(got, ref), (rel(got, ref), maxrel(got, ref))
     oref = oracle.observables(cfg, ref)
     for k in ("E", "N", "rms"):
         assert abs(obs[k] - oref[k]) < TOL * abs(oref[k]), k
@@ -150,7 +160,7 @@ def test_2d_real_workload_grid():
     got, obs = gpu_run(psi0, w.dx, w.dy, False, 3, **p)
     cfg = ocfg(2, w.nx, w.ny, w.dx, w.dy, False, **p)
     ref = oracle.step(cfg, psi0, 3)
-    assert rel(got, ref) < TOL
+    assert close(got, ref), (rel(got, ref), maxrel(got, ref))
     oref = oracle.observables(cfg, ref)
     for k in ("E", "N", "M", "rms"):
         if abs(oref[k]) < 1e-2:
@@ -189,7 +199,7 @@ def test_step_real_seq_matches_in_place_steps():
     assert g.step_index == 5
     for k in range(5):
         ref = oracle.step(ocfg(2, nx, ny, dx, dx, False, **p), psi0, k + 1)
-        assert rel(dst[k].cpu().numpy(), ref) < TOL
+        assert close(dst[k].cpu().numpy(), ref)
     np.testing.assert_array_equal(src.cpu().numpy(), psi0)
 
 
@@ -207,7 +217,7 @@ def test_omega_schedule_follows_step_index():
     ref = psi0
     for n in range(14):
         ref = oracle.step(ocfg(2, nx, ny, dx, dx, False, **{**p, "omega": sched[min(n // 4, 2)]}), ref, 1)
-    assert rel(t.cpu().numpy(), ref) < TOL
+    assert close(t.cpu().numpy(), ref)
 
 
 def test_runs_are_bitwise_reproducible():
