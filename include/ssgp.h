@@ -201,6 +201,22 @@ int ssgp_obs_log_reserve(ssgp_grid g, int capacity);
 int ssgp_obs_record(ssgp_grid g);
 int ssgp_obs_log_read(ssgp_grid g, ssgp_obs *out, int max, int *count);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * observables of ssgp_observables for a state that no grid holds, with no
+ * device or host allocation by the library.  psi_dev: 3*ny*nx elements of
+ * dtype in the layout above (device memory, read only); dim, nx, ny, dx, dy
+ * as for ssgp_create_grid (1 <= nx, ny <= 2048, ny ignored in 1D); p as for
+ * ssgp_set_params (checked the same way), its omega used for the Rabi part;
+ * hip_stream as for ssgp_create_grid.  The partial sums live in a fixed
+ * device array of the library (about 96 KiB, one per GPU, kept until the
+ * process ends): calls that overlap on one GPU (other streams or threads)
+ * race on it and must be serialised by the caller.  Synchronises the stream;
+ * SSGP_ENONFINITE as for ssgp_observables. */
+int ssgp_observables_noalloc(int dim, int nx, int ny, double dx, double dy, int dtype,
+                             const void *psi_dev, const ssgp_params *p, void *hip_stream,
+                             ssgp_obs *out);
+
 /* Adjoint of real-time steps (reverse-mode derivative in the convention
  * grad = dL/dRe(psi) + i dL/dIm(psi)).  states_dev holds the nsteps step
  * inputs psi^{n0}, ..., psi^{n0+nsteps-1} contiguously, where n0 + nsteps is

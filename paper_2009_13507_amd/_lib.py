@@ -76,6 +76,8 @@ def load():
         "ssgp_obs_log_reserve": ([G, ci], ci),
         "ssgp_obs_record": ([G], ci),
         "ssgp_obs_log_read": ([G, ctypes.POINTER(Obs), ci, ctypes.POINTER(ci)], ci),
+        "ssgp_observables_noalloc": ([ci, ci, ci, cd, cd, ci, vp, ctypes.POINTER(Params), vp,
+                                      ctypes.POINTER(Obs)], ci),
         "ssgp_step_real_adjoint": ([G, vp, vp, ci], ci),
         "ssgp_omega_grad": ([G, ctypes.POINTER(cd), ci, ci], ci),
         "ssgp_destroy": ([G], ci),

@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -279,6 +280,10 @@ static unsigned nz_mask(const cd *m) {
         if (m[q] != cd(0.0, 0.0)) b |= 1u << q;
     return b;
 }
+
+// workgroups of the observables pass (each leaves OBS_NQ partial sums)
+constexpr int OBS_MAX_BLOCKS = 1024;
+static int obs_blocks(long long plane) { return (int)std::min<long long>((plane + 255) / 256, OBS_MAX_BLOCKS); }
 
 // --------------------------------------------------------------- grid ---
 enum { MODE_REAL = 0, MODE_IMAG = 1, MODE_ADJ = 2, NMODES = 3 };
@@ -829,7 +834,7 @@ template <typename R> static int step_real_t(ssgp_grid g, const void *src, void 
 }
 
 // ---------------------------------------------------------------- ABI ---
-static int check_params(const GridCore &g, const ssgp_params *p) {
+static int check_params(int dim, int scheme, const ssgp_params *p) {
     if (!p) return fail(SSGP_EINVAL, "params is NULL");
     const double v[] = {p->c0, p->c2, p->gamma, p->omega, p->kappa, p->dt, p->mag0};
     for (double x : v)
@@ -838,14 +843,16 @@ static int check_params(const GridCore &g, const ssgp_params *p) {
     if (p->so < SSGP_SO_NONE || p->so > SSGP_SO_ERD) return fail(SSGP_EINVAL, "unknown so form %d", p->so);
     if (p->renorm < SSGP_RENORM_AUTO || p->renorm > SSGP_RENORM_FIXED_M)
         return fail(SSGP_EINVAL, "unknown renorm rule %d", p->renorm);
-    if (g.dim == 1 && so_has_y(p->so)) return fail(SSGP_EINVAL, "y-dependent SO form on a 1D grid");
-    if (g.dim == 2 && (p->so == SSGP_SO_PX_SY || p->so == SSGP_SO_PX_SZ))
+    if (dim == 1 && so_has_y(p->so)) return fail(SSGP_EINVAL, "y-dependent SO form on a 1D grid");
+    if (dim == 2 && (p->so == SSGP_SO_PX_SY || p->so == SSGP_SO_PX_SZ))
         return fail(SSGP_EINVAL, "SO form %d is defined for 1D grids", p->so);
     if (std::fabs(p->mag0) > 1.0) return fail(SSGP_EINVAL, "|mag0| must be <= 1");
-    if (g.scheme == SSGP_SCHEME_UNITARY_SO && so_y_terms(p->so))
+    if (scheme == SSGP_SCHEME_UNITARY_SO && so_y_terms(p->so))
         return fail(SSGP_EINVAL, "the unitary-SO scheme takes the forms without y derivatives");
     return SSGP_OK;
 }
+
+static int check_params(const GridCore &g, const ssgp_params *p) { return check_params(g.dim, g.scheme, p); }
 
 extern "C" int ssgp_create_grid(int dim, int nx, int ny, double dx, double dy, int dtype, void *psi_dev,
                                 void *hip_stream, ssgp_grid *out) {
@@ -880,7 +887,7 @@ extern "C" int ssgp_create_grid(int dim, int nx, int ny, double dx, double dy, i
     const int ntiles = (nx + YTX - 1) / YTX;
     int rc = g->partials.ensure(sizeof(double) * 3 * ntiles);
     if (rc == SSGP_OK) rc = g->renorm.ensure(sizeof(double) * 8);
-    if (rc == SSGP_OK) rc = g->obs_partials.ensure(sizeof(double) * OBS_NQ * 1024);
+    if (rc == SSGP_OK) rc = g->obs_partials.ensure(sizeof(double) * OBS_NQ * OBS_MAX_BLOCKS);
     if (rc == SSGP_OK) rc = g->obs_out.ensure(sizeof(double) * 16);
     if (rc == SSGP_OK) rc = g->omega_acc.ensure(sizeof(double) * 1);
     if (rc != SSGP_OK) {
@@ -984,41 +991,49 @@ extern "C" int ssgp_step_real_seq(ssgp_grid g, const void *src, void *dst, int n
                                  : step_real_t<float>(g, src, dst, nsteps, true);
 }
 
-// Launches the observables pass over psi; the 12 fixed-order sums go to
-// out_dev (device memory).  E_rabi takes the Omega of the last step taken
-// (GridCore::obs_omega).
-template <typename R> static int observables_launch(ssgp_grid g, const void *psi, double *out_dev) {
+// Arguments of the observables pass over psi (Eqs. (4)-(5)) with Rabi
+// strength omega.
+template <typename R>
+static ObsArgs<R> obs_args(int dim, int nx, int ny, double dx, double dy, const ssgp_params &p, double omega,
+                           const void *psi) {
     ObsArgs<R> a{};
     a.psi = static_cast<const cx<R> *>(psi);
-    a.dim = g->dim;
-    a.nx = g->nx;
-    a.ny = g->dim == 2 ? g->ny : 1;
-    a.plane = plane_of(*g);
-    a.dx = g->dx;
-    a.dy = g->dy;
-    a.x0 = -0.5 * g->nx * g->dx;
-    a.y0 = g->dim == 2 ? -0.5 * g->ny * g->dy : 0.0;
-    a.kappa2 = g->p.kappa * g->p.kappa;
-    a.c0 = g->p.c0;
-    a.c2 = g->p.c2;
-    a.om_t = g->obs_omega / std::sqrt(2.0);
-    const SOForm f = so_form(g->p.so, g->p.gamma);
+    a.dim = dim;
+    a.nx = nx;
+    a.ny = dim == 2 ? ny : 1;
+    a.plane = (long long)nx * a.ny;
+    a.dx = dx;
+    a.dy = dy;
+    a.x0 = -0.5 * nx * dx;
+    a.y0 = dim == 2 ? -0.5 * ny * dy : 0.0;
+    a.kappa2 = p.kappa * p.kappa;
+    a.c0 = p.c0;
+    a.c2 = p.c2;
+    a.om_t = omega / std::sqrt(2.0);
+    const SOForm f = so_form(p.so, p.gamma);
     for (int q = 0; q < 9; ++q) {
         a.hx[q] = cx<double>{f.hx[q].real(), f.hx[q].imag()};
         a.hy[q] = cx<double>{f.hy[q].real(), f.hy[q].imag()};
     }
-    a.hxmask = g->p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hx);
-    a.hymask = g->p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hy);
+    a.hxmask = p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hx);
+    a.hymask = p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hy);
+    return a;
+}
+
+// Launches the observables pass over psi; the 12 fixed-order sums go to
+// out_dev (device memory).  E_rabi takes the Omega of the last step taken
+// (GridCore::obs_omega).
+template <typename R> static int observables_launch(ssgp_grid g, const void *psi, double *out_dev) {
+    ObsArgs<R> a = obs_args<R>(g->dim, g->nx, g->ny, g->dx, g->dy, g->p, g->obs_omega, psi);
     a.partials = g->obs_partials.as<double>();
-    const int nb = (int)std::min<long long>((a.plane + 255) / 256, 1024);
+    const int nb = obs_blocks(a.plane);
     LAUNCH_TRY(launch_obs<R>(lc(*g), a, nb));
     LAUNCH_TRY(launch_obs_finalize(lc(*g), g->obs_partials.as<double>(), nb, out_dev));
     return SSGP_OK;
 }
 
-// ssgp_obs from the 12 sums of the observables pass.
-static int obs_from_sums(const GridCore &g, const double *h, ssgp_obs *out) {
-    const double dA = darea(g);
+// ssgp_obs from the 12 sums of the observables pass (dA the area element).
+static int obs_from_sums(double dA, const double *h, ssgp_obs *out) {
     ssgp_obs o{};
     for (int j = 0; j < 3; ++j) o.N[j] = h[j] * dA;
     o.Ntot = o.N[0] + o.N[1] + o.N[2];
@@ -1038,7 +1053,7 @@ template <typename R> static int observables_t(ssgp_grid g, const void *psi, ssg
     double h[OBS_NQ];
     HIP_TRY(hipMemcpyAsync(h, g->obs_out.p, sizeof h, hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
-    return obs_from_sums(*g, h, out);
+    return obs_from_sums(darea(*g), h, out);
 }
 
 extern "C" int ssgp_observables(ssgp_grid g, ssgp_obs *out) {
@@ -1079,7 +1094,7 @@ extern "C" int ssgp_obs_log_read(ssgp_grid g, ssgp_obs *out, int max, int *count
     *count = g->obs_log_used;
     int rc = SSGP_OK;
     for (int k = 0; k < n; ++k) {
-        const int r = obs_from_sums(*g, h.data() + (size_t)OBS_NQ * k, out + k);
+        const int r = obs_from_sums(darea(*g), h.data() + (size_t)OBS_NQ * k, out + k);
         if (r != SSGP_OK && rc == SSGP_OK) rc = r;
     }
     return rc;
@@ -1155,3 +1170,69 @@ extern "C" int ssgp_profile_read(ssgp_grid g, double *out) {
 
 #include "adjoint_host.inl"
 #include "batch_host.inl"
+
+// ------------------------------------------ observables, no allocation ---
+// For callers that cannot allocate device memory: the observables pass's
+// partial sums and its result live in this file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never passes the array's
+// name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, once per
+// device, on the first call with that device current.
+constexpr int NOALLOC_DOUBLES = OBS_NQ * OBS_MAX_BLOCKS + OBS_NQ;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static double *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static std::once_flag g_scratch_once[NOALLOC_MAX_DEVICES];
+static hipError_t g_scratch_err[NOALLOC_MAX_DEVICES];
+
+static int scratch_on_current_device(double **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(SSGP_EDEVICE, "device %d beyond the supported %d", dev, NOALLOC_MAX_DEVICES);
+    std::call_once(g_scratch_once[dev], [dev]() {
+        void *p = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    });
+    if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev])
+        return fail(SSGP_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(g_scratch_err[dev]));
+    *out = g_scratch_ptr[dev];
+    return SSGP_OK;
+}
+
+template <typename R>
+static int observables_noalloc_t(int dim, int nx, int ny, double dx, double dy, const void *psi,
+                                 const ssgp_params &p, hipStream_t st, ssgp_obs *out) {
+    double *buf = nullptr;
+    SSGP_TRY(scratch_on_current_device(&buf));
+    ObsArgs<R> a = obs_args<R>(dim, nx, ny, dx, dy, p, p.omega, psi);
+    const int nb = obs_blocks(a.plane);
+    if (nb > OBS_MAX_BLOCKS) return fail(SSGP_EINVAL, "observables need %d partial blocks, scratch holds %d", nb, OBS_MAX_BLOCKS);
+    a.partials = buf;                                 // [nb][OBS_NQ], every slot written by its block
+    double *sums = buf + OBS_NQ * OBS_MAX_BLOCKS;     // the OBS_NQ final sums
+    const Launch c{st, 1};
+    LAUNCH_TRY(launch_obs<R>(c, a, nb));
+    LAUNCH_TRY(launch_obs_finalize(c, buf, nb, sums));
+    double h[OBS_NQ];
+    HIP_TRY(hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return obs_from_sums(dim == 2 ? dx * dy : dx, h, out);
+}
+
+extern "C" int ssgp_observables_noalloc(int dim, int nx, int ny, double dx, double dy, int dtype,
+                                        const void *psi_dev, const ssgp_params *p, void *hip_stream,
+                                        ssgp_obs *out) {
+    if (!out || !psi_dev) return fail(SSGP_EINVAL, "NULL argument");
+    if (dim != 1 && dim != 2) return fail(SSGP_EINVAL, "dim must be 1 or 2");
+    if (dtype != SSGP_C128 && dtype != SSGP_C64) return fail(SSGP_EINVAL, "unknown dtype %d", dtype);
+    if (dim == 1) ny = 1;
+    if (nx < 1 || nx > 2048 || ny < 1 || ny > 2048)
+        return fail(SSGP_EINVAL, "nx, ny must be in [1, 2048] (got %d, %d)", nx, ny);
+    if (!(dx > 0) || !std::isfinite(dx) || (dim == 2 && (!(dy > 0) || !std::isfinite(dy))))
+        return fail(SSGP_EINVAL, "grid spacing must be positive");
+    SSGP_TRY(check_params(dim, SSGP_SCHEME_PAPER, p));
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    return dtype == SSGP_C128 ? observables_noalloc_t<double>(dim, nx, ny, dx, dim == 2 ? dy : 1.0, psi_dev, *p, st, out)
+                              : observables_noalloc_t<float>(dim, nx, ny, dx, dim == 2 ? dy : 1.0, psi_dev, *p, st, out);
+}
