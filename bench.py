@@ -10,8 +10,9 @@ Prints one JSON line:
   value      grid-point-steps per second over the timed steps (state resident
              in HBM when the timed region starts; the observables are recorded
              into a device-side log inside the timed region and read after it;
-             the warm-up runs the timed schedule once, so every graph the timed
-             steps replay is captured beforehand);
+             the warm-up runs the timed schedule untimed for at least 0.3 s, so
+             every graph the timed steps replay is captured beforehand and the
+             GPU runs at its working clocks);
   roofline   the dominant kernel's algorithmic bytes per launch over its mean
              duration (HIP start/stop events attached to its launches on the
              library's stream, every 7th step of a window of at least 50
@@ -32,7 +33,6 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -358,6 +358,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--warmup-seconds", type=float, default=0.3,
+                    help="after the W warm-up steps, repeat the timed schedule untimed for at least this long")
     ap.add_argument("--obs-every", type=int, default=100)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--profile-every", type=int, default=0,
@@ -408,11 +410,19 @@ def main():
             if done % args.obs_every == 0:
                 g.obs_record()
 
-    # warm-up: W steps, then the timed schedule once (so that every graph
-    # length it replays is captured beforehand); then back to the initial state
+    # warm-up: W steps, then the timed schedule, repeated for at least
+    # --warmup-seconds of wall time (every graph length it replays is
+    # captured beforehand, and the GPU leaves its idle clocks); then back to
+    # the initial state
     g.step_real(args.warmup)
-    g.obs_log_reserve(nobs)
-    run(K)
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    while True:
+        g.obs_log_reserve(nobs)
+        run(K)
+        torch.cuda.synchronize()
+        if time.perf_counter() - tw >= args.warmup_seconds:
+            break
     g.obs_log_reserve(nobs)
     state.copy_(init)
     g.step_index = 0
