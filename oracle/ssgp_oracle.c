@@ -395,6 +395,69 @@ void ora_step(const ora_cfg *c, cplx *psi, long nsteps)
     }
 }
 
+/* ------------------------------------------- second-order pointwise stage */
+/* Opt-in second-order (Strang) scheme, beyond the paper.  The pointwise part
+ * of Eqs. (1)-(2) (trap and density terms, c2 and Rabi couplings) is the flow
+ * psi' = -k (Phi(psi) + A(psi)) psi at every point, Phi = diag(phi_j) of
+ * CALCNU and A the matrix of HERM (App. A, Eq. (eq:nu)).  CALCNU and HERM
+ * take Phi and A frozen at their input, which is first order in the step for
+ * c2 != 0.  This stage integrates the flow over tau by the exponential
+ * midpoint rule:
+ *   1. predictor: psi_m = HERM(tau/2) CALCNU(tau/2) psi (the paper's two
+ *      sub-steps over half the interval);
+ *   2. Phi_m = Phi(psi_m), A_m = A(psi_m);
+ *   3. psi <- exp(-k tau/2 Phi_m) exp(-k tau A_m) exp(-k tau/2 Phi_m) psi,
+ *      the symmetric product of the two frozen exponentials.
+ * psi_m is within O(tau^2) of the exact midpoint value, so the stage has a
+ * local error O(tau^3).  The exponentials are those of CALCNU (the exp of
+ * each diagonal entry) and HERM (the power series of exp(z A_m) above). */
+static void phi_point(const ora_cfg *c, double V, const cplx v[3], double phi[3])
+{
+    double rp = creal(v[0]) * creal(v[0]) + cimag(v[0]) * cimag(v[0]);
+    double r0 = creal(v[1]) * creal(v[1]) + cimag(v[1]) * cimag(v[1]);
+    double rm = creal(v[2]) * creal(v[2]) + cimag(v[2]) * cimag(v[2]);
+    double rho = rp + r0 + rm;
+    phi[0] = V + c->c0 * rho + c->c2 * (rp - rm + r0);
+    phi[1] = V + c->c0 * rho + c->c2 * (rp + rm);
+    phi[2] = V + c->c0 * rho + c->c2 * (rm - rp + r0);
+}
+
+static void ab_point(const ora_cfg *c, const cplx v[3], cplx *a, cplx *b)
+{
+    double om = c->omega / sqrt(2.0);
+    *a = c->c2 * conj(v[2]) * v[1] + om;
+    *b = c->c2 * conj(v[1]) * v[0] + om;
+}
+
+void ora_pointwise2(const ora_cfg *c, cplx *psi, double tau)
+{
+    size_t np = npts(c);
+    cplx k = kfac(c);
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < (long)np; p++) {
+        int ix = (int)(p % c->nx), iy = (int)(p / c->nx);
+        double x = xc(c, ix), y = yc(c, iy);
+        double V = 0.5 * (x * x + c->kappa * c->kappa * y * y);
+        cplx v[3] = { psi[p], psi[np + p], psi[2 * np + p] };
+        /* 1. predictor over tau/2 */
+        cplx m[3] = { v[0], v[1], v[2] };
+        double phi[3];
+        cplx a, b;
+        phi_point(c, V, m, phi);
+        for (int j = 0; j < 3; j++) m[j] *= cexp(-k * (0.5 * tau) * phi[j]);
+        ab_point(c, m, &a, &b);
+        herm_point(a, b, -k * (0.5 * tau), m);
+        /* 2. coefficients at the midpoint */
+        phi_point(c, V, m, phi);
+        ab_point(c, m, &a, &b);
+        /* 3. symmetric product of the frozen exponentials */
+        for (int j = 0; j < 3; j++) v[j] *= cexp(-k * (0.5 * tau) * phi[j]);
+        herm_point(a, b, -k * tau, v);
+        for (int j = 0; j < 3; j++) v[j] *= cexp(-k * (0.5 * tau) * phi[j]);
+        psi[p] = v[0]; psi[np + p] = v[1]; psi[2 * np + p] = v[2];
+    }
+}
+
 /* ----------------------------------------------------------- observables */
 /* out[0..15] = N+1, N0, N-1, N, M, E, E_kin, E_trap, E_c0, E_c2, E_rabi, E_so,
  *              rms+1, rms0, rms-1, rms_total.
