@@ -79,8 +79,9 @@ enum ssgp_renorm { SSGP_RENORM_AUTO = 0, SSGP_RENORM_NORM = 1, SSGP_RENORM_FIXED
 /* Time-stepping scheme (ssgp_set_scheme).  PAPER: the splitting of Sec. 2 and
  * App. A, with the explicit SO sub-step of Eqs. (p1)-(p2).  UNITARY_SO (opt-in,
  * beyond the paper): the SO term is taken by Crank-Nicolson together with the
- * x kinetic term. */
-enum ssgp_scheme { SSGP_SCHEME_PAPER = 0, SSGP_SCHEME_UNITARY_SO = 1 };
+ * x kinetic term.  STRANG (opt-in, beyond the paper): a second-order splitting
+ * around the same joined solve. */
+enum ssgp_scheme { SSGP_SCHEME_PAPER = 0, SSGP_SCHEME_UNITARY_SO = 1, SSGP_SCHEME_STRANG = 2 };
 
 typedef struct {
     double c0, c2;     /* density couplings of Eqs. (1)-(2)                 */
@@ -131,12 +132,24 @@ int ssgp_set_params(ssgp_grid g, const ssgp_params *p);
  * and LUX of Table 1 joined, S_a the spin-1 matrix of Eq. (3), central
  * differences, zero ghosts), then LUY (2D) and, in imaginary time, RENORM.
  * In real time the step then conserves the norm exactly for gamma != 0.  The
- * library solves each line in the eigenbasis of S_a.  EINVAL for an unknown
- * scheme or parameters with a y-derivative SO form (ssgp_set_params then
- * refuses those too); a step call returns EINVAL when the symmetrised line
- * matrix is not diagonally dominant (real time: dt gamma >= 2 dx).
- * The adjoint entry points (ssgp_step_real_seq, ssgp_step_real_adjoint)
- * return ESTATE under this scheme.  Drops the captured step graphs. */
+ * library solves each line in the eigenbasis of S_a.
+ * SSGP_SCHEME_STRANG, for the same SO forms: each step is P2(dt/2), the
+ * joined x solve and LUY of UNITARY_SO, P2(dt/2), then RENORM in imaginary
+ * time (and in real time with ssgp_set_renorm_real).  P2(tau) takes the
+ * pointwise part of Eqs. (1)-(2) (CALCNU's diagonal terms and HERM's matrix of
+ * App. A) over tau by the exponential midpoint rule: a predictor
+ * psi_m = HERM(tau/2) CALCNU(tau/2) psi, then exp(-k tau/2 Phi(psi_m))
+ * exp(-k tau A(psi_m)) exp(-k tau/2 Phi(psi_m)) psi.  The step is second order
+ * in dt (the paper's splitting is first order).  On 2D grids in real time the
+ * last P2 of a step is merged into the next step's x-pass and the last one of
+ * a call (or of an Omega segment) runs as its own pass; with RENORM it runs as
+ * its own pass every step.
+ * Both: EINVAL for an unknown scheme or parameters with a y-derivative SO
+ * form (ssgp_set_params then refuses those too); a step call returns EINVAL
+ * when the symmetrised line matrix is not diagonally dominant (real time:
+ * dt gamma >= 2 dx).  The adjoint entry points (ssgp_step_real_seq,
+ * ssgp_step_real_adjoint) return ESTATE under these schemes.  Drops the
+ * captured step graphs. */
 int ssgp_set_scheme(ssgp_grid g, int scheme);
 
 /* on = 1: apply the RENORM rule (Eqs. (DJ)/(DJ2), as chosen by the renorm

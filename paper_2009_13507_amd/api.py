@@ -18,7 +18,7 @@ SO_NONE, SO_PX_SX, SO_PX_SY, SO_PX_SZ, SO_RASHBA, SO_DRESSELHAUS, SO_ERD = range
 RENORM_AUTO, RENORM_NORM, RENORM_FIXED_M = range(3)
 # PAPER: the paper's splitting; UNITARY_SO (opt-in): the SO term by
 # Crank-Nicolson together with the x kinetic term (the p_x Sigma forms)
-SCHEME_PAPER, SCHEME_UNITARY_SO = range(2)
+SCHEME_PAPER, SCHEME_UNITARY_SO, SCHEME_STRANG = range(3)
 
 
 def _dtype_code(t: torch.Tensor) -> int:

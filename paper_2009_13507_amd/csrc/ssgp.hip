@@ -456,7 +456,7 @@ template <typename R> static int build_tables(ssgp_grid g, int mode) {
     const cd s = cn_s(mode, g->p.dt);
     const int Lx = x_chunk(g->nx);
     SSGP_TRY(upload_cn<R>(T.x[mode], cn_tables(g->nx, g->dx, s, Lx, 64, 6), g->nx, Lx, 64, g->stream));
-    const bool uso = g->scheme == SSGP_SCHEME_UNITARY_SO && mode != MODE_ADJ;
+    const bool uso = g->scheme != SSGP_SCHEME_PAPER && mode != MODE_ADJ;  // the joined x solve
     if (g->dim == 1 && uso) SSGP_TRY(build_uso<R>(g, mode, Lx, 64));
     if (g->dim == 2) {
         const int km = x_block(g->nx);
@@ -562,7 +562,8 @@ static XArgs<R> x_args(ssgp_grid g, int mode, const void *src, void *dst, double
     fill_so(a, *g, mode);
     a.so_y = 0;
     a.ramp = nullptr;
-    if (g->scheme == SSGP_SCHEME_UNITARY_SO && g->dim == 2 && mode != MODE_ADJ) {
+    if (g->scheme != SSGP_SCHEME_PAPER && g->dim == 2 && mode != MODE_ADJ) {
+        a.strang = g->scheme == SSGP_SCHEME_STRANG ? 1 : 0;
         a.ramp = T.ramp[mode].template as<cx<R>>();
         for (int q = 0; q < 9; ++q) a.rot[q] = tor<R>(g->uso_rot[q]);
         for (int c = 0; c < 3; ++c) {
@@ -598,22 +599,64 @@ static RenormSpec renorm_spec(const GridCore &g) {
 
 template <typename R> static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps);
 
+// Workgroups of the element-wise kernels over a plane of n points.
 static int ew_blocks(long long n) { return (int)std::min<long long>((n + 255) / 256, 2048); }
 
-// One 2D step from src into dst (dst may equal src except with a
-// y-derivative SO form).  Imaginary time (and real time with renorm_real):
-// with renorm_prev the RENORM of the previous step (whose y-pass left its
-// tile partials in g->partials) is applied first, reduced inside the x-pass;
-// the y-pass leaves this step's partials.
+// Number of |psi|^2 partials the RENORM of a step reduces: per y-pass tile,
+// or (Strang scheme) per workgroup of its closing pointwise pass.
+static int renorm_tiles(const GridCore &g) {
+    return g.scheme == SSGP_SCHEME_STRANG ? ew_blocks(plane_of(g)) : (g.nx + YTX - 1) / YTX;
+}
+
+// Whether a step of this mode continues work left by the step before it:
+// the RENORM of the previous step (imaginary time, or real time with
+// renorm_real) or, Strang scheme in real time without RENORM, the previous
+// step's closing P2(dt/2), merged into this step's x-pass.
+static bool uses_cont(const GridCore &g, int mode) {
+    return g.renorms(mode) || (g.scheme == SSGP_SCHEME_STRANG && mode == MODE_REAL);
+}
+
+// The closing P2(dt/2) of the Strang scheme over psi, in place; with
+// partials, the |psi_j|^2 sums of the result per workgroup (for RENORM).
 template <typename R>
-static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omega, bool renorm_prev) {
+static int strang_close(ssgp_grid g, int mode, void *psi, double omega, double *partials) {
+    PArgs<R> pa{};
+    pa.psi = static_cast<cx<R> *>(psi);
+    pa.src = nullptr;
+    pa.nx = g->nx;
+    pa.ny = g->ny;
+    pa.plane = plane_of(*g);
+    pa.dx = (R)g->dx;
+    pa.dy = (R)g->dy;
+    pa.x0 = (R)(-0.5 * g->nx * g->dx);
+    pa.y0 = (R)(-0.5 * g->ny * g->dy);
+    pa.m = model<R>(*g, mode, omega);
+    pa.m.dt = (R)(0.5 * g->p.dt);
+    pa.dscale = nullptr;
+    pa.p2 = 1;
+    pa.norm_partials = partials;
+    LAUNCH_TRY(launch_pointwise<R>(lc(*g), pa, ew_blocks(pa.plane)));
+    return SSGP_OK;
+}
+
+// One 2D step from src into dst (dst may equal src except with a
+// y-derivative SO form).  cont (see uses_cont): the step continues a run.
+// Imaginary time (and real time with renorm_real): with cont the RENORM of
+// the previous step (whose last pass left its partials in g->partials) is
+// applied first, reduced inside the x-pass; this step leaves its own
+// partials.  Strang scheme: the x-pass applies P2(dt/2), twice with cont in
+// real time without RENORM (the previous step's closing stage and this
+// step's opening one); with RENORM the step closes with its own P2 pass.
+template <typename R>
+static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omega, bool cont) {
     const bool rn = g->renorms(mode);
-    renorm_prev = renorm_prev && rn;
+    const bool renorm_prev = cont && rn;
+    const bool strang = g->scheme == SSGP_SCHEME_STRANG;
     hipEvent_t *ev = nullptr;
     if (g->prof_every > 0 && (g->prof_counter++ % g->prof_every) == 0 && g->prof_used < g->prof_cap)
         ev = &g->prof_events[(size_t)4 * g->prof_used++];
     const YShape ys = y_shape(g->ny);
-    const int ntiles = (g->nx + YTX - 1) / YTX;
+    const int rtiles = renorm_tiles(*g);
     if (so_y_terms(g->p.so) && g->p.gamma != 0.0) {
         // pointwise pass from src into scratch, then SO(x,y) + CN_x from scratch
         const size_t bytes = (size_t)3 * plane_of(*g) * sizeof(cx<R>);
@@ -631,7 +674,7 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
         pa.m = model<R>(*g, mode, omega);
         pa.dscale = nullptr;
         if (renorm_prev) {
-            LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), ntiles, renorm_spec(*g),
+            LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), rtiles, renorm_spec(*g),
                                               g->renorm.as<double>()));
             pa.dscale = g->renorm.as<double>();
         }
@@ -644,13 +687,15 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
         XArgs<R> xa = x_args<R>(g, mode, src, dst, omega, nullptr);
         if (renorm_prev) {
             xa.rpart = g->partials.as<double>();
-            xa.rntiles = ntiles;
+            xa.rntiles = rtiles;
             xa.rsp = renorm_spec(*g);
         }
+        if (strang) xa.pointwise = (cont && !rn) ? 2 : 1;
         SSGP_TRY(launch_x<R>(*g, xa, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     }
-    YArgs<R> ya = y_args<R>(g, mode, dst, rn ? g->partials.as<double>() : nullptr);
+    YArgs<R> ya = y_args<R>(g, mode, dst, (rn && !strang) ? g->partials.as<double>() : nullptr);
     SSGP_TRY(launch_y<R>(*g, ya, ys, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
+    if (strang && rn) SSGP_TRY(strang_close<R>(g, mode, dst, omega, g->partials.as<double>()));
     return SSGP_OK;
 }
 
@@ -675,7 +720,7 @@ static int step_graph(ssgp_grid g, int mode, int k, bool renorm_first, double om
     hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         for (int s = 0; s < k && rc == SSGP_OK; ++s)
-            rc = step2d<R>(g, mode, g->psi, g->psi, omega, g->renorms(mode) && (renorm_first || s > 0));
+            rc = step2d<R>(g, mode, g->psi, g->psi, omega, uses_cont(*g, mode) && (renorm_first || s > 0));
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(g->cap, &graph);
         if (e == hipSuccess && rc == SSGP_OK) {
@@ -697,11 +742,12 @@ static int step_graph(ssgp_grid g, int mode, int k, bool renorm_first, double om
 
 // n in-place 2D steps of g->psi at a fixed Omega.  Runs of steps go out as
 // graph replays (runs of 2^i <= 64 steps), except steps whose kernels are
-// timed, which are launched one by one.  Imaginary time (and real time with
-// renorm_real): every step but (unless renorm_first) the first applies the
-// previous step's RENORM.
-template <typename R> static int run_steps(ssgp_grid g, int mode, int n, double omega, bool renorm_first) {
-    if (!g->renorms(mode)) renorm_first = false;
+// timed, which are launched one by one.  Every step but the first continues
+// the run (uses_cont); the first does when cont_first is set (the RENORM left
+// by an earlier call's steps).  Strang scheme in real time without RENORM:
+// the run ends with the closing P2(dt/2) of its last step as its own pass.
+template <typename R> static int run_steps(ssgp_grid g, int mode, int n, double omega, bool cont_first) {
+    if (!g->renorms(mode)) cont_first = false;
     const bool graphable = g->dim == 2;
     // the y-derivative SO forms' pointwise pass writes a scratch copy:
     // allocate it before any capture
@@ -709,9 +755,10 @@ template <typename R> static int run_steps(ssgp_grid g, int mode, int n, double 
         SSGP_TRY(g->scratch.ensure((size_t)3 * plane_of(*g) * sizeof(cx<R>)));
     int s = 0;
     while (s < n) {
+        const bool cont = uses_cont(*g, mode) && (cont_first || s > 0);
         const bool timing = g->prof_every > 0 && g->prof_used < g->prof_cap;
         if (!graphable || (timing && g->prof_counter % g->prof_every == 0)) {
-            SSGP_TRY(step2d<R>(g, mode, g->psi, g->psi, omega, g->renorms(mode) && (renorm_first || s > 0)));
+            SSGP_TRY(step2d<R>(g, mode, g->psi, g->psi, omega, cont));
             ++s;
             continue;
         }
@@ -720,11 +767,13 @@ template <typename R> static int run_steps(ssgp_grid g, int mode, int n, double 
         int p = 1;
         while (p * 2 <= std::min(k, STEP_GRAPH_MAX)) p *= 2;
         hipGraphExec_t exec = nullptr;
-        SSGP_TRY(step_graph<R>(g, mode, p, g->renorms(mode) && (renorm_first || s > 0), omega, &exec));
+        SSGP_TRY(step_graph<R>(g, mode, p, cont, omega, &exec));
         HIP_TRY(hipGraphLaunch(exec, g->stream));
         if (g->prof_every > 0) g->prof_counter += p;
         s += p;
     }
+    if (n > 0 && g->scheme == SSGP_SCHEME_STRANG && !g->renorms(mode))
+        SSGP_TRY(strang_close<R>(g, mode, g->psi, omega, nullptr));
     return SSGP_OK;
 }
 
@@ -747,7 +796,8 @@ template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int
     a.renorm_out = g->renorm.as<double>();
     a.renorm = g->renorms(mode) ? 1 : 0;
     a.ramp = nullptr;
-    if (g->scheme == SSGP_SCHEME_UNITARY_SO && mode != MODE_ADJ) {
+    if (g->scheme != SSGP_SCHEME_PAPER && mode != MODE_ADJ) {
+        a.strang = g->scheme == SSGP_SCHEME_STRANG ? 1 : 0;
         a.ramp = T.ramp[mode].template as<cx<R>>();
         for (int q = 0; q < 9; ++q) a.rot[q] = tor<R>(g->uso_rot[q]);
         for (int c = 0; c < 3; ++c) {
@@ -760,9 +810,9 @@ template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int
     return SSGP_OK;
 }
 
-// The RENORM of the last 2D step of a call (its y-pass left the partials).
+// The RENORM of the last 2D step of a call (its last pass left the partials).
 template <typename R> static int final_renorm(ssgp_grid g) {
-    LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), (g->nx + YTX - 1) / YTX, renorm_spec(*g),
+    LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), renorm_tiles(*g), renorm_spec(*g),
                                       g->renorm.as<double>()));
     LAUNCH_TRY(launch_scale<R>(lc(*g), static_cast<cx<R> *>(g->psi), plane_of(*g), g->renorm.as<double>(),
                                ew_blocks(plane_of(*g))));
@@ -847,8 +897,8 @@ static int check_params(int dim, int scheme, const ssgp_params *p) {
     if (dim == 2 && (p->so == SSGP_SO_PX_SY || p->so == SSGP_SO_PX_SZ))
         return fail(SSGP_EINVAL, "SO form %d is defined for 1D grids", p->so);
     if (std::fabs(p->mag0) > 1.0) return fail(SSGP_EINVAL, "|mag0| must be <= 1");
-    if (scheme == SSGP_SCHEME_UNITARY_SO && so_y_terms(p->so))
-        return fail(SSGP_EINVAL, "the unitary-SO scheme takes the forms without y derivatives");
+    if (scheme != SSGP_SCHEME_PAPER && so_y_terms(p->so))
+        return fail(SSGP_EINVAL, "the unitary-SO and Strang schemes take the forms without y derivatives");
     return SSGP_OK;
 }
 
@@ -884,7 +934,9 @@ extern "C" int ssgp_create_grid(int dim, int nx, int ny, double dx, double dy, i
             return fail(SSGP_EDEVICE, "cannot query the device");
         }
     }
-    const int ntiles = (nx + YTX - 1) / YTX;
+    // RENORM partials: per y-pass tile, or per workgroup of the Strang
+    // scheme's closing pointwise pass
+    const int ntiles = std::max((nx + YTX - 1) / YTX, ew_blocks((long long)nx * ny));
     int rc = g->partials.ensure(sizeof(double) * 3 * ntiles);
     if (rc == SSGP_OK) rc = g->renorm.ensure(sizeof(double) * 8);
     if (rc == SSGP_OK) rc = g->obs_partials.ensure(sizeof(double) * OBS_NQ * OBS_MAX_BLOCKS);
@@ -922,10 +974,10 @@ extern "C" int ssgp_set_params(ssgp_grid g, const ssgp_params *p) {
 
 extern "C" int ssgp_set_scheme(ssgp_grid g, int scheme) {
     if (!g) return fail(SSGP_EINVAL, "grid is NULL");
-    if (scheme != SSGP_SCHEME_PAPER && scheme != SSGP_SCHEME_UNITARY_SO)
+    if (scheme != SSGP_SCHEME_PAPER && scheme != SSGP_SCHEME_UNITARY_SO && scheme != SSGP_SCHEME_STRANG)
         return fail(SSGP_EINVAL, "unknown scheme %d", scheme);
-    if (scheme == SSGP_SCHEME_UNITARY_SO && g->have_params && so_y_terms(g->p.so))
-        return fail(SSGP_EINVAL, "the unitary-SO scheme takes the forms without y derivatives");
+    if (scheme != SSGP_SCHEME_PAPER && g->have_params && so_y_terms(g->p.so))
+        return fail(SSGP_EINVAL, "the unitary-SO and Strang schemes take the forms without y derivatives");
     if (scheme != g->scheme) {
         g->clear_graphs();
         g->built_mode_mask = 0;

@@ -143,6 +143,17 @@ __device__ __forceinline__ void herm_apply(cx<R> &p, cx<R> &z, cx<R> &m, cx<R> a
     }
 }
 
+// HERM with given off-diagonals a, b and q = u^2 = dt^2 (|a|^2 + |b|^2) / 4:
+// the shortest series every lane of the wavefront allows.
+template <typename R>
+__device__ __forceinline__ void herm_with(cx<R> &p, cx<R> &z, cx<R> &m, cx<R> a, cx<R> b, R q, const Model<R> &M) {
+    R S, C;
+    if (__all(q <= R(SERIES_Q2))) herm_sc<R, 2>(q, M.imag, S, C);
+    else if (__all(q <= R(SERIES_Q4))) herm_sc<R, 4>(q, M.imag, S, C);
+    else herm_sc<R, 0>(q, M.imag, S, C);
+    herm_apply(p, z, m, a, b, S, C, M);
+}
+
 template <typename R>
 __device__ __forceinline__ void pointwise(cx<R> &p, cx<R> &z, cx<R> &m, R V, const Model<R> &M) {
     R th[3];
@@ -162,11 +173,52 @@ __device__ __forceinline__ void pointwise(cx<R> &p, cx<R> &z, cx<R> &m, R V, con
     }
     cx<R> a, b;
     const R q = herm_ab(p, z, m, M, a, b);
-    R S, C;
-    if (__all(q <= R(SERIES_Q2))) herm_sc<R, 2>(q, M.imag, S, C);
-    else if (__all(q <= R(SERIES_Q4))) herm_sc<R, 4>(q, M.imag, S, C);
-    else herm_sc<R, 0>(q, M.imag, S, C);
-    herm_apply(p, z, m, a, b, S, C, M);
+    herm_with(p, z, m, a, b, q, M);
+}
+
+// Second-order pointwise stage over tau = M.dt (the opt-in Strang scheme,
+// beyond the paper).  CALCNU and HERM take their coefficients frozen at
+// their input, which is first order for c2 != 0; here the flow
+// psi' = -k (Phi(psi) + A(psi)) psi is taken by the exponential midpoint
+// rule: a predictor psi_m = HERM(tau/2) CALCNU(tau/2) psi (the sub-steps
+// above over half the interval), Phi and A evaluated at psi_m, and
+//   psi <- exp(-k tau/2 Phi_m) exp(-k tau A_m) exp(-k tau/2 Phi_m) psi
+// (the two diagonal factors are the same numbers, computed once).
+template <typename R>
+__device__ __forceinline__ void pointwise2(cx<R> &p, cx<R> &z, cx<R> &m, R V, const Model<R> &M) {
+    Model<R> Mh = M;
+    Mh.dt = R(0.5) * M.dt;
+    cx<R> mp = p, mz = z, mm = m;
+    pointwise(mp, mz, mm, V, Mh);
+    R th[3];
+    calcnu_phases(mp, mz, mm, V, Mh, th);
+    cx<R> a, b;
+    const R q = herm_ab(mp, mz, mm, M, a, b);
+    if (M.imag) {
+        const R e0 = exp_(-th[0]), e1 = exp_(-th[1]), e2 = exp_(-th[2]);
+        p = e0 * p;
+        z = e1 * z;
+        m = e2 * m;
+        herm_with(p, z, m, a, b, q, M);
+        p = e0 * p;
+        z = e1 * z;
+        m = e2 * m;
+    } else {
+        R c, s;
+        cos_sin(th[0], c, s);
+        const cx<R> e0 = mk(c, -s);
+        cos_sin(th[1], c, s);
+        const cx<R> e1 = mk(c, -s);
+        cos_sin(th[2], c, s);
+        const cx<R> e2 = mk(c, -s);
+        p = p * e0;
+        z = z * e1;
+        m = m * e2;
+        herm_with(p, z, m, a, b, q, M);
+        p = p * e0;
+        z = z * e1;
+        m = m * e2;
+    }
 }
 
 // -------------------------------------------------- chunked line solve ---
@@ -539,7 +591,8 @@ template <typename R> struct XArgs {
     const double *rpart;       // or: the previous y-pass's tile partials [3][rntiles],
     int rntiles;               //     reduced here into the factors (rsp: the rule)
     RenormSpec rsp;
-    int pointwise;             // 1: CALCNU + HERM in this pass
+    int pointwise;             // 1: CALCNU + HERM in this pass (the second-order
+                               //    kernels: the number of P2(dt/2) stages, 1 or 2)
     LineCoef<R> cx_;           // CN_x elimination coefficients (256 chunks of KM points)
     cx<R> rdiag;               // diagonal of (I - sT)/o (off-diagonal -1)
     cx<R> qx[9];               // SO: psi'_j += sum_j' qx[j][j'] (psi_j'(i+1) - psi_j'(i-1))
@@ -557,6 +610,7 @@ template <typename R> struct XArgs {
     cx<R> rot[9];
     LineCoef<R> cu[3];
     cx<R> rdiag_u[3];
+    int strang;                // 1: the second-order pointwise stages (with ramp)
 };
 
 constexpr int XPASS_THREADS = 256;
@@ -726,7 +780,7 @@ __device__ __forceinline__ void store_row(cx<R> *dst, long long plane, int nx, c
 
 // Everything after the loads, for one row whose KM points per thread are in
 // v (zero beyond nx).
-template <typename R, int KM, int CM, bool FULL, bool SOY, bool USO>
+template <typename R, int KM, int CM, bool FULL, bool SOY, bool USO, bool P2>
 __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)[3][KM], XShared<R, KM> &sh) {
     cx<R> *E = sh.E;
     auto &scA = sh.scA;
@@ -781,7 +835,15 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
                     v[1][k] = d1 * v[1][k];
                     v[2][k] = d2 * v[2][k];
                 }
-                if (a.pointwise) {
+                if constexpr (P2) {
+                    // a.pointwise stages P2(dt/2): the previous step's last
+                    // and this step's first, or this step's first only
+                    const R xv = a.x0 + R(i) * a.dx;
+                    Model<R> Mt = a.m;
+                    Mt.dt = R(0.5) * a.m.dt;
+                    for (int rep = 0; rep < a.pointwise; ++rep)
+                        pointwise2(v[0][k], v[1][k], v[2][k], R(0.5) * xv * xv + vy, Mt);
+                } else if (a.pointwise) {
                     const R xv = a.x0 + R(i) * a.dx;
                     pointwise(v[0][k], v[1][k], v[2][k], R(0.5) * xv * xv + vy, a.m);
                 }
@@ -999,10 +1061,11 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
 // 36.6 against 39.4 us.  The y-derivative SO form at 4 points per thread
 // spills at 4 wavefronts per SIMD and runs faster at 2: 42.2 against 54.3 us
 // at 1024^2.)
-template <typename R, int KM, int CM, bool FULL, bool SOY, bool USO = false>
+template <typename R, int KM, int CM, bool FULL, bool SOY, bool USO = false, bool P2 = false>
 __global__ void __launch_bounds__(XPASS_THREADS)
-__attribute__((amdgpu_waves_per_eu(USO ? (KM <= 1 || (KM <= 4 && CM != 0) ? 4 : 2)
-                                       : (KM <= 4 ? (SOY && KM == 4 ? 2 : 4) : 1))))
+__attribute__((amdgpu_waves_per_eu(P2 ? (KM <= 4 ? 2 : 1)
+                                   : USO ? (KM <= 1 || (KM <= 4 && CM != 0) ? 4 : 2)
+                                         : (KM <= 4 ? (SOY && KM == 4 ? 2 : 4) : 1))))
 xpass_kernel(XArgs<R> a) {
     __shared__ XShared<R, KM> sh;
     const int nx = FULL ? XPASS_THREADS * KM : a.nx;
@@ -1016,7 +1079,7 @@ xpass_kernel(XArgs<R> a) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) v[j][k] = (FULL || i < nx) ? src[j * a.plane + i] : czero<R>();
     }
-    xpass_row<R, KM, CM, FULL, SOY, USO>(a, row, v, sh);
+    xpass_row<R, KM, CM, FULL, SOY, USO, P2>(a, row, v, sh);
 }
 
 // ------------------------------------------------------------- y-pass ---
@@ -1161,7 +1224,10 @@ __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
 // ------------------------------------------------ pointwise-only pass ---
 // Used ahead of an x-pass that reads neighbouring rows (y-derivative SO):
 // RENORM scale, CALCNU and HERM, from src (or in place when src is null)
-// into psi.
+// into psi.  With p2 set instead: the second-order stage P2 over m.dt (the
+// last stage of a step of the opt-in Strang scheme), and, with norm_partials,
+// each workgroup's sums of |psi_j|^2 of the result in
+// norm_partials[j * gridDim.x + block] (for the RENORM that follows).
 template <typename R> struct PArgs {
     cx<R> *psi;
     const cx<R> *src;
@@ -1170,11 +1236,14 @@ template <typename R> struct PArgs {
     R dx, dy, x0, y0;
     Model<R> m;
     const double *dscale;
+    int p2;
+    double *norm_partials;
 };
 
-template <typename R>
+template <typename R, bool P2>
 __global__ void __launch_bounds__(256) pointwise_kernel(PArgs<R> a) {
     const long long n = a.plane;
+    double nrm[3] = {0.0, 0.0, 0.0};
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x) {
         const int ix = (int)(q % a.nx), iy = (int)(q / a.nx);
@@ -1186,10 +1255,33 @@ __global__ void __launch_bounds__(256) pointwise_kernel(PArgs<R> a) {
             m = R(a.dscale[2]) * m;
         }
         const R xv = a.x0 + R(ix) * a.dx, yv = a.y0 + R(iy) * a.dy;
-        pointwise(p, z, m, R(0.5) * (xv * xv + a.m.kappa2 * yv * yv), a.m);
+        const R V = R(0.5) * (xv * xv + a.m.kappa2 * yv * yv);
+        if constexpr (P2) pointwise2(p, z, m, V, a.m);
+        else pointwise(p, z, m, V, a.m);
         a.psi[q] = p;
         a.psi[n + q] = z;
         a.psi[2 * n + q] = m;
+        if constexpr (P2) {
+            nrm[0] += (double)abs2(p);
+            nrm[1] += (double)abs2(z);
+            nrm[2] += (double)abs2(m);
+        }
+    }
+    if (P2 && a.norm_partials) {
+        __shared__ double red[3][4];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double t = nrm[j];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) t += __shfl_down(t, d, 64);
+            if (lane == 0) red[j][wave] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            const int j = threadIdx.x;
+            a.norm_partials[(long long)j * gridDim.x + blockIdx.x] = red[j][0] + red[j][1] + red[j][2] + red[j][3];
+        }
     }
 }
 
@@ -1226,6 +1318,7 @@ template <typename R> struct Args1D {
     cx<R> rot[9];
     LineCoef<R> cu[3];
     cx<R> rdiag_u[3];
+    int strang;                // 1: Strang scheme (with ramp)
 };
 
 // USO: the unitary-SO scheme (each wavefront solves its line of the state
@@ -1233,7 +1326,9 @@ template <typename R> struct Args1D {
 // state is rotated back in LDS before the RENORM norms).
 // The line-solve coefficients are read once into registers (per-lane
 // pivots, CM = 0 form): they do not change during the run.
-template <typename R, int L, bool USO = false>
+// P2 (with USO): the opt-in Strang scheme, P2(dt/2) before the solve and
+// after it (before RENORM), in LDS.
+template <typename R, int L, bool USO = false, bool P2 = false>
 __global__ void __launch_bounds__(step1d_threads(L)) step1d_kernel(Args1D<R> a) {
     constexpr int NT = step1d_threads(L);
     extern __shared__ unsigned char smem_raw[];
@@ -1266,7 +1361,13 @@ __global__ void __launch_bounds__(step1d_threads(L)) step1d_kernel(Args1D<R> a) 
             const int si = sidx<L>(i);
             cx<R> p = s[si], z = s[ld + si], m = s[2 * ld + si];
             const R xv = a.x0 + R(i) * a.dx;
-            pointwise(p, z, m, R(0.5) * xv * xv, a.m);
+            if constexpr (P2) {
+                Model<R> Mt = a.m;
+                Mt.dt = R(0.5) * a.m.dt;
+                pointwise2(p, z, m, R(0.5) * xv * xv, Mt);
+            } else {
+                pointwise(p, z, m, R(0.5) * xv * xv, a.m);
+            }
             if constexpr (USO) {
                 const cx<R> v[3] = {p, z, m};
                 cx<R> w[3];
@@ -1302,9 +1403,18 @@ __global__ void __launch_bounds__(step1d_threads(L)) step1d_kernel(Args1D<R> a) 
             for (int i = tid; i < nx; i += NT) {
                 const int si = sidx<L>(i);
                 const cx<R> w0 = s[si], w1 = s[ld + si], w2 = s[2 * ld + si];
-                s[si] = a.rot[0] * w0 + a.rot[1] * w1 + a.rot[2] * w2;
-                s[ld + si] = a.rot[3] * w0 + a.rot[4] * w1 + a.rot[5] * w2;
-                s[2 * ld + si] = a.rot[6] * w0 + a.rot[7] * w1 + a.rot[8] * w2;
+                cx<R> p = a.rot[0] * w0 + a.rot[1] * w1 + a.rot[2] * w2;
+                cx<R> z = a.rot[3] * w0 + a.rot[4] * w1 + a.rot[5] * w2;
+                cx<R> m = a.rot[6] * w0 + a.rot[7] * w1 + a.rot[8] * w2;
+                if constexpr (P2) {
+                    const R xv = a.x0 + R(i) * a.dx;
+                    Model<R> Mt = a.m;
+                    Mt.dt = R(0.5) * a.m.dt;
+                    pointwise2(p, z, m, R(0.5) * xv * xv, Mt);
+                }
+                s[si] = p;
+                s[ld + si] = z;
+                s[2 * ld + si] = m;
             }
             __syncthreads();
             if (solver) {
