@@ -23,7 +23,8 @@ Prints one JSON line:
              threads and with one, and the CPU model.
 Beside them: the forward+adjoint cost ratio, the batched-vs-serial
 comparison, the imaginary-time workloads, the same 1024^2 workload under the
-opt-in unitary-SO scheme (unitary_so), with the Rashba coupling (rashba_step)
+opt-in unitary-SO scheme (unitary_so) and Strang scheme (strang_step), with the
+Rashba coupling (rashba_step)
 and in complex64 (complex64_step, with its difference from complex128).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -230,6 +231,43 @@ def unitary_so(steps: int = 1000, warmup: int = 50, every: int = 7):
     npts = w.nx * w.ny
     per_launch = BYTES_PER_PT_PASS["f64"] * npts
     return {"workload": w.name + " (unitary-SO scheme)", "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "pt_steps_per_s": npts * steps / el,
+            "kernels_ms": {"xpass": prof["x_ms"], "ypass": prof["y_ms"], "profiled_steps": prof["steps"]},
+            "xpass_achieved_GBs": per_launch / (prof["x_ms"] * 1e-3) / 1e9,
+            "norm_change": n1 - n0}
+
+
+def strang_step(steps: int = 1000, warmup: int = 50, every: int = 7):
+    """The 1024^2 real-time workload under the opt-in Strang scheme (second
+    order; the second-order pointwise stages merged into the x-pass, the
+    joined x solve, the y-pass, and one closing pointwise pass per call):
+    step rate, kernel times (HIP events on every `every`-th step) and the
+    x-pass rate on its algorithmic bytes."""
+    import torch
+
+    from paper_2009_13507_amd import api
+    from paper_2009_13507_amd import workloads as W
+
+    w = W.W2D_REAL
+    state = torch.from_numpy(W.initial_2d_real(w)).to("cuda:0")
+    g = api.Grid(state, w.dx, w.dy)
+    g.set_params(c0=w.c0, c2=w.c2, gamma=w.gamma, omega=w.omega, dt=w.dt, so=w.so)
+    g.set_scheme(api.SCHEME_STRANG)
+    g.step_real(warmup)
+    n0 = g.observables()["N"]
+    g.profile(every, capacity=steps // every + 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step_real(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = g.profile_read()
+    g.profile(0)
+    n1 = g.observables()["N"]
+    g.close()
+    npts = w.nx * w.ny
+    per_launch = BYTES_PER_PT_PASS["f64"] * npts
+    return {"workload": w.name + " (Strang scheme)", "steps": steps, "ms_per_step": 1e3 * el / steps,
             "pt_steps_per_s": npts * steps / el,
             "kernels_ms": {"xpass": prof["x_ms"], "ypass": prof["y_ms"], "profiled_steps": prof["steps"]},
             "xpass_achieved_GBs": per_launch / (prof["x_ms"] * 1e-3) / 1e9,
@@ -485,6 +523,7 @@ def main():
         line["adjoint_cost_ratio"] = adjoint_ratio()
     if not args.no_uso and args.dtype == "f64":
         line["unitary_so"] = unitary_so()
+        line["strang_step"] = strang_step()
         line["rashba_step"] = rashba_step()
     if not args.no_batch and args.dtype == "f64":
         line["complex64_step"] = complex64_step()
