@@ -4,10 +4,8 @@
 // Per step, over all instances of the batch:
 //   X phase, items (instance, row): RENORM scale of the previous step,
 //      CALCNU, HERM, SO, the Crank-Nicolson right-hand side and the x-line
-//      solve of one row (one item per 4-wavefront workgroup: the pointwise
-//      part in a coalesced layout, then each component line transposed
-//      through LDS into 64 chunks and solved by one wavefront; for rows of at
-//      most 512 points this measured faster than the single-grid row code);
+//      solve of one row, all by one wavefront (batch_xrow_wave: each lane
+//      owns L consecutive points of the three components, no barrier);
 //   Y phase, items (instance, component, tile of TX columns): the y-line
 //      solve (chunks in registers, chunk scans across the workgroup) and the
 //      tile's sum of |psi|^2;
@@ -104,33 +102,36 @@ __device__ __forceinline__ bool grid_sync(unsigned *bar, long long spin_limit) {
 
 // Shared memory of one workgroup.
 template <typename R> struct BatchSmem {
-    cx<R> line[64 * BATCH_MAX_LX + 64 + 1];  // one staged row, one padding slot per chunk
-    cx<R> edge[48];                          // x edge exchange: [2][4 waves][2 ends][3 comps]
+    cx<R> line[64 * BATCH_MAX_LX + 64 + 1];  // the y pivot head
     cx<R> scA[2][4][BatchTX<R>::v], scB[2][4][BatchTX<R>::v];
     double red[3][BATCH_THREADS];
 };
 
-// One x row of one instance (the single-grid x-pass algorithm, 4 waves).
+// One x row of one instance by one wavefront (rows of at most 64 L points).
+// Lane l owns the L consecutive points l L .. l L + L - 1 of all three
+// components from the loads to the stores: RENORM scale, CALCNU + HERM, the
+// SO update and the right-hand side in registers (the values just outside a
+// lane's points come from the neighbouring lanes by DPP rotations; the row
+// ends are the zero ghosts), then the three lines' chunk eliminations, one
+// affine-map scan per sweep within the wavefront and the carry fix-ups (the
+// same elimination as the 4-wavefront row code: 64 chunks of L points), and
+// coalesced stores through the wavefront's own LDS line.  No barrier: the
+// wavefronts of a workgroup work on different rows.
+template <typename R, int L> constexpr int bx_line_slots() { return 64 * L + 64; }
 template <typename R, int L>
-__device__ __forceinline__ void batch_xrow(const BatchInst<R> &I, cx<R> *psi, int row, const double *dscale,
-                                           BatchSmem<R> &S) {
-    constexpr int KM = (64 * L + BATCH_THREADS - 1) / BATCH_THREADS;
-    cx<R> *B = S.line;
-    cx<R> *E = S.edge;
+__device__ __forceinline__ void batch_xrow_wave(const BatchInst<R> &I, cx<R> *psi, int row, const double *dscale,
+                                                cx<R> *line) {
+    const int lane = threadIdx.x & 63;
     const int nx = I.nx;
     const long long plane = (long long)nx * I.ny;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int K = (nx + BATCH_THREADS - 1) / BATCH_THREADS;
-    const int RW = 64 * K;
+    const int i0 = lane * L;
+    const int len = max(0, min(L, nx - i0));
     cx<R> *rowp = psi + (long long)row * nx;
-    cx<R> v[3][KM];
+    cx<R> v[3][L];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const int i = w * RW + 64 * k + lane;
-        const bool ok = k < K && i < nx;
+    for (int t = 0; t < L; ++t)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) v[j][k] = ok ? rowp[j * plane + i] : czero<R>();
-    }
+        for (int j = 0; j < 3; ++j) v[j][t] = t < len ? rowp[j * plane + i0 + t] : czero<R>();
     {
         R d0 = R(1), d1 = R(1), d2 = R(1);
         if (dscale) {
@@ -141,110 +142,131 @@ __device__ __forceinline__ void batch_xrow(const BatchInst<R> &I, cx<R> *psi, in
         const R yv = I.y0 + R(row) * I.dy;
         const R vy = R(0.5) * I.m.kappa2 * yv * yv;
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int i = w * RW + 64 * k + lane;
-            if (k < K && i < nx) {
+        for (int t = 0; t < L; ++t) {
+            if (t < len) {
                 if (dscale) {
-                    v[0][k] = d0 * v[0][k];
-                    v[1][k] = d1 * v[1][k];
-                    v[2][k] = d2 * v[2][k];
+                    v[0][t] = d0 * v[0][t];
+                    v[1][t] = d1 * v[1][t];
+                    v[2][t] = d2 * v[2][t];
                 }
-                const R xv = I.x0 + R(i) * I.dx;
-                pointwise(v[0][k], v[1][k], v[2][k], R(0.5) * xv * xv + vy, I.m);
+                const R xv = I.x0 + R(i0 + t) * I.dx;
+                pointwise(v[0][t], v[1][t], v[2][t], R(0.5) * xv * xv + vy, I.m);
             }
         }
     }
-    auto exchange_edges = [&](cx<R> (&x)[3][KM], int round) {
-        cx<R> *Er = E + round * 24;
-#pragma unroll
-        for (int k = 0; k < KM; ++k)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                if (lane == 0 && k == 0) Er[(w * 2 + 0) * 3 + j] = x[j][k];
-                if (lane == 63 && k == K - 1) Er[(w * 2 + 1) * 3 + j] = x[j][k];
-            }
+    // values just outside this lane's points (zero beyond the row's ends)
+    auto outer = [&](const cx<R> (&x)[L], cx<R> &before, cx<R> &after) {
+        before = ror1(x[L - 1]);
+        after = rol1(x[0]);
+        if (lane == 0) before = czero<R>();
+        if (lane == 63) after = czero<R>();
     };
-    auto neighbours = [&](cx<R> (&x)[3][KM], int round, int j, int k, cx<R> &prev, cx<R> &next) {
-        const cx<R> *Er = E + round * 24;
-        const cx<R> r0 = ror1(x[j][k]);
-        const cx<R> rm = ror1(x[j][k > 0 ? k - 1 : 0]);
-        const cx<R> l0 = rol1(x[j][k]);
-        const cx<R> lp = rol1(x[j][k + 1 < KM ? k + 1 : k]);
-        prev = r0;
-        next = l0;
-        if (lane == 0) prev = k > 0 ? rm : (w > 0 ? Er[((w - 1) * 2 + 1) * 3 + j] : czero<R>());
-        if (lane == 63) next = k < K - 1 ? lp : (w < 3 ? Er[((w + 1) * 2 + 0) * 3 + j] : czero<R>());
-    };
-    // SO update
-    exchange_edges(v, 0);
-    __syncthreads();
-    cx<R> u[3][KM];
+    // SO update u = v + q (v(i+1) - v(i-1))
+    cx<R> u[3][L];
+    {
+        cx<R> vb[3], va[3];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        cx<R> pv[3], nv[3];
+        for (int jp = 0; jp < 3; ++jp) outer(v[jp], vb[jp], va[jp]);
 #pragma unroll
-        for (int jp = 0; jp < 3; ++jp) neighbours(v, 0, jp, k, pv[jp], nv[jp]);
-        const int i = w * RW + 64 * k + lane;
-        const bool ok = k < K && i < nx;
+        for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            cx<R> t = v[j][k];
+            for (int t = 0; t < L; ++t) u[j][t] = v[j][t];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int jp = 0; jp < 3; ++jp)
-                if (I.qxmask & (1u << (3 * j + jp))) t = cfma(I.qx[3 * j + jp], nv[jp] - pv[jp], t);
-            u[j][k] = ok ? t : czero<R>();
-        }
+                if (I.qxmask & (1u << (3 * j + jp))) {
+                    const cx<R> q = I.qx[3 * j + jp];
+#pragma unroll
+                    for (int t = 0; t < L; ++t) {
+                        const cx<R> pv = t > 0 ? v[jp][t > 0 ? t - 1 : 0] : vb[jp];
+                        const cx<R> nv = t + 1 < L ? v[jp][t + 1 < L ? t + 1 : 0] : va[jp];
+                        u[j][t] = cfma(q, nv - pv, u[j][t]);
+                    }
+                }
+#pragma unroll
+        for (int t = 0; t < L; ++t)
+            if (t >= len)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) u[j][t] = czero<R>();
     }
     // right-hand side (I - sT) u / o
-    exchange_edges(u, 1);
-    __syncthreads();
-    cx<R> r[3][KM];
+    cx<R> r[3][L];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const int i = w * RW + 64 * k + lane;
-        const bool ok = k < K && i < nx;
+    for (int j = 0; j < 3; ++j) {
+        cx<R> ub, ua;
+        outer(u[j], ub, ua);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            cx<R> pu, nu;
-            neighbours(u, 1, j, k, pu, nu);
-            r[j][k] = ok ? cn_rhs(I.rdx, u[j][k], pu + nu) : czero<R>();
+        for (int t = 0; t < L; ++t) {
+            const cx<R> pu = t > 0 ? u[j][t > 0 ? t - 1 : 0] : ub;
+            const cx<R> nu = t + 1 < L ? u[j][t + 1 < L ? t + 1 : 0] : ua;
+            r[j][t] = t < len ? cn_rhs(I.rdx, u[j][t], pu + nu) : czero<R>();
         }
     }
-    // transpose into the chunk layout, solve (waves 0-2), transpose back
-    const int start = lane * L;
-    const int len = max(0, min(L, nx - start));
-    cx<R> c[L];
+    // the three lines: chunk eliminations, scans within the wavefront, fix-ups
+    const ChunkCoef<R, L, 0> cpl(I.lx, i0);
+    const cx<R> Ak = I.lx.chunkA[lane];
+    cx<R> A[3], B[3], carry[3];
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-        __syncthreads();
+    for (int j = 0; j < 3; ++j) {
+        A[j] = Ak;
+        B[j] = fwd_local<R, L>(r[j], len, cpl);
+    }
+    wave_scan_up3<R>(A, B, I.lx.levels);
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int i = w * RW + 64 * k + lane;
-            if (k < K && i < nx) B[sidx<L>(i)] = r[jj][k];
-        }
-        __syncthreads();
-        if (w == jj) {
+    for (int j = 0; j < 3; ++j) {
+        carry[j] = shfl_up(B[j], 1);
+        if (lane == 0) carry[j] = czero<R>();
+    }
+    fwd_fix3<R, L, 0>(r, len, cpl, carry);
 #pragma unroll
-            for (int t = 0; t < L; ++t) c[t] = t < len ? B[sidx<L>(start + t)] : czero<R>();
+    for (int j = 0; j < 3; ++j) {
+        A[j] = Ak;
+        B[j] = bwd_local<R, L>(r[j], len, cpl);
+    }
+    wave_scan_down3<R>(A, B, I.lx.levels);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        carry[j] = shfl_down(B[j], 1);
+        if (lane == 63) carry[j] = czero<R>();
+    }
+    bwd_fix3<R, L, 0>(r, len, cpl, carry);
+    // coalesced stores (store k of lane l: point 64 k + l)
+    if constexpr (L == 1) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (len > 0) rowp[j * plane + lane] = r[j][0];
+    } else {
+        cx<R> c0[L], c1[L], c2[L];
+        wave_exchange<R, L>(line, lane, r[0], c0);
+        wave_exchange<R, L>(line, lane, r[1], c1);
+        wave_exchange<R, L>(line, lane, r[2], c2);
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const int i = 64 * k + lane;
+            if (i < nx) {
+                put2(rowp + i, c0[k]);
+                put2(rowp + plane + i, c1[k]);
+                put2(rowp + 2 * plane + i, c2[k]);
+            }
         }
     }
-    if (w < 3) solve_line_wave<R, L, 0>(c, start, len, I.lx);
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-        __syncthreads();
-        if (w == jj) {
-#pragma unroll
-            for (int t = 0; t < L; ++t)
-                if (t < len) B[sidx<L>(start + t)] = c[t];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int i = w * RW + 64 * k + lane;
-            if (k < K && i < nx) rowp[jj * plane + i] = B[sidx<L>(i)];
-        }
+}
+
+// x item of one wavefront (row q of the work list).
+template <typename R>
+__device__ __forceinline__ void batch_x_item_wave(const BatchArgs<R> &a, int q, bool apply_renorm, cx<R> *line) {
+    const int it = a.x_items[q];
+    const int inst = it >> 10, row = it & 1023;
+    const BatchInst<R> &I = a.inst[inst];
+    cx<R> *psi = a.pool + I.off;
+    const double *ds = apply_renorm ? a.renorm + (long long)inst * 8 : nullptr;
+    switch (I.Lx) {
+    case 1: batch_xrow_wave<R, 1>(I, psi, row, ds, line); break;
+    case 2: batch_xrow_wave<R, 2>(I, psi, row, ds, line); break;
+    case 4: batch_xrow_wave<R, 4>(I, psi, row, ds, line); break;
+    default: batch_xrow_wave<R, 8>(I, psi, row, ds, line); break;
     }
-    __syncthreads();  // the shared buffers are reused by the next item
 }
 
 // Elimination coefficients of a y chunk read from an LDS copy of the pivot
@@ -381,21 +403,6 @@ template <typename R> __device__ __forceinline__ void batch_renorm_item(const Ba
 
 // ------------------------------------------------------------- items ---
 template <typename R>
-__device__ __forceinline__ void batch_x_item(const BatchArgs<R> &a, int q, bool apply_renorm, BatchSmem<R> &S) {
-    const int it = a.x_items[q];
-    const int inst = it >> 10, row = it & 1023;
-    const BatchInst<R> &I = a.inst[inst];
-    cx<R> *psi = a.pool + I.off;
-    const double *ds = apply_renorm ? a.renorm + (long long)inst * 8 : nullptr;
-    switch (I.Lx) {
-    case 1: batch_xrow<R, 1>(I, psi, row, ds, S); break;
-    case 2: batch_xrow<R, 2>(I, psi, row, ds, S); break;
-    case 4: batch_xrow<R, 4>(I, psi, row, ds, S); break;
-    default: batch_xrow<R, 8>(I, psi, row, ds, S); break;
-    }
-}
-
-template <typename R>
 __device__ __forceinline__ void batch_y_item(const BatchArgs<R> &a, int q, BatchSmem<R> &S) {
     const int it = a.y_items[q];
     const int inst = it >> 8, j = (it >> 6) & 3, tile = it & 63;
@@ -431,8 +438,12 @@ template <typename R> __device__ __forceinline__ void batch_scale_item(const Bat
 template <typename R>
 __global__ void __launch_bounds__(BATCH_THREADS) batch_persistent_kernel(BatchArgs<R> a) {
     __shared__ BatchSmem<R> S;
+    __shared__ cx<R> xlines[BATCH_THREADS / 64][bx_line_slots<R, BATCH_MAX_LX>()];
+    const int wave = threadIdx.x >> 6;
     for (int step = 0; step < a.nsteps; ++step) {
-        for (int q = blockIdx.x; q < a.nrows; q += gridDim.x) batch_x_item(a, q, step > 0, S);
+        // x rows, one per wavefront
+        for (int q = blockIdx.x * (BATCH_THREADS / 64) + wave; q < a.nrows; q += gridDim.x * (BATCH_THREADS / 64))
+            batch_x_item_wave(a, q, step > 0, xlines[wave]);
         if (!grid_sync(a.bar, a.spin_limit)) return;
         for (int q = blockIdx.x; q < a.nyitems; q += gridDim.x) batch_y_item(a, q, S);
         if (!grid_sync(a.bar, a.spin_limit)) return;
@@ -443,11 +454,15 @@ __global__ void __launch_bounds__(BATCH_THREADS) batch_persistent_kernel(BatchAr
         for (int q = blockIdx.x; q < a.nrows; q += gridDim.x) batch_scale_item(a, q);
 }
 
-// One launch per phase: one workgroup per item.
+// One launch per phase: one workgroup per item (x rows: one wavefront per
+// row, BATCH_XWAVES rows per workgroup).
+constexpr int BATCH_XWAVES = 4;
 template <typename R>
-__global__ void __launch_bounds__(BATCH_THREADS) batch_x_kernel(BatchArgs<R> a, int apply_renorm) {
-    __shared__ BatchSmem<R> S;
-    batch_x_item(a, blockIdx.x, apply_renorm != 0, S);
+__global__ void __launch_bounds__(64 * BATCH_XWAVES) batch_x_kernel(BatchArgs<R> a, int apply_renorm) {
+    __shared__ cx<R> xlines[BATCH_XWAVES][bx_line_slots<R, BATCH_MAX_LX>()];
+    const int wave = threadIdx.x >> 6;
+    const int q = blockIdx.x * BATCH_XWAVES + wave;
+    if (q < a.nrows) batch_x_item_wave(a, q, apply_renorm != 0, xlines[wave]);
 }
 
 template <typename R>
