@@ -31,7 +31,7 @@ struct ssgp_batch_s {
     size_t pool_bytes = 0;      // extent of the pool the instances use
     hipStream_t stream = nullptr, cap = nullptr;
     std::vector<ssgp_grid> grids;
-    int nrows = 0, nyitems = 0, ntiles = 0;
+    int nrows = 0, nrows2 = 0, nyitems = 0, ntiles = 0;
     DevBuf xitems, yitems, partials, renorm, bar;
     BatchTabs<double> t64;
     BatchTabs<float> t32;
@@ -96,6 +96,7 @@ template <typename R> static int batch_build(ssgp_batch b, const long long *offs
         I.y0 = xa.y0;
         I.m = xa.m;
         I.lx = tables<R>(g).x[MODE_IMAG].coef();
+        I.lv4 = cn_tables(g->nx, g->dx, cn_s(MODE_IMAG, g->p.dt), 4, 128, 6).levels;
         I.ly = T.ly[i].coef();
         I.rdx = xa.rdiag;
         I.rdy = T.ly[i].rdiag;
@@ -121,6 +122,11 @@ template <typename R> static int batch_build(ssgp_batch b, const long long *offs
         for (int j = 0; j < 3; ++j)
             for (int t = 0; t < host[i].ntiles; ++t) yi.push_back((i << 8) | (j << 6) | t);
     b->nrows = (int)xi.size();
+    // rows by two wavefronts (x chunk of 8 points) come first in the list
+    b->nrows2 = 0;
+    if (batch_pair_rows<R>())
+        for (int q : xi)
+            if (host[q >> 10].Lx == 8) ++b->nrows2;
     b->nyitems = (int)yi.size();
     SSGP_TRY(b->xitems.ensure(sizeof(int) * xi.size()));
     SSGP_TRY(b->yitems.ensure(sizeof(int) * yi.size()));
@@ -144,6 +150,7 @@ template <typename R> static BatchArgs<R> batch_args(ssgp_batch b, void *pool, i
     a.x_items = b->xitems.as<int>();
     a.y_items = b->yitems.as<int>();
     a.nrows = b->nrows;
+    a.nrows2 = b->nrows2;
     a.nyitems = b->nyitems;
     a.partials = b->partials.as<double>();
     a.renorm = b->renorm.as<double>();

@@ -47,6 +47,7 @@ template <typename R> struct BatchInst {
     R dx, dy, x0, y0;
     Model<R> m;
     LineCoef<R> lx, ly;        // elimination coefficients of the x and y lines
+    int lv4;                   // scan levels of x lines in chunks of 4 points (two-wavefront rows)
     cx<R> rdx, rdy;            // diagonal of (I - sT)/o of x and y (off-diagonal -1)
     cx<R> qx[9];               // SO: psi'_j += sum_j' qx[j][j'] (psi_j'(i+1) - psi_j'(i-1))
     unsigned qxmask;
@@ -59,6 +60,7 @@ template <typename R> struct BatchArgs {
     const int *x_items;        // (instance << 10) | row
     const int *y_items;        // (instance << 8) | (component << 6) | tile
     int nrows, nyitems;
+    int nrows2;                // x_items[0, nrows2): rows by two wavefronts (batch_xrow_pair)
     double *partials;          // [total tiles][3] tile sums of |psi|^2
     double *renorm;            // [instances][8]: d[3], N[3], fallback
     int ninst;
@@ -253,6 +255,195 @@ __device__ __forceinline__ void batch_xrow_wave(const BatchInst<R> &I, cx<R> *ps
     }
 }
 
+// Rows by two wavefronts (in double precision the rows of 257..512 points,
+// whose one-wavefront form needs the registers of two).  Thread t of the
+// pair owns the 4 consecutive points 4 t .. 4 t + 3: as batch_xrow_wave, with
+// the values across the two wavefronts' boundary and the chunk maps of the
+// first (forward) or second (backward) wavefront passed through LDS; the line
+// is eliminated in 128 chunks of 4 points, each lane's chunk product formed
+// from its pivots.  Every thread of the workgroup calls it the same number of
+// times (it holds barriers); `active` is false for a pair with no row.
+template <typename R> constexpr bool batch_pair_rows() { return sizeof(R) == 8; }
+
+template <typename R> struct PairSmem {
+    cx<R> E[2][2][2][3];           // [round][wave][end][component]
+    cx<R> scA[2][2][3], scB[2][2][3];  // [sweep][wave][component]
+};
+
+template <typename R>
+__device__ __forceinline__ void batch_xrow_pair(const BatchInst<R> &I, cx<R> *psi, int row, const double *dscale,
+                                                cx<R> *line, PairSmem<R> &P, bool active) {
+    constexpr int L = 4;
+    const int tid = threadIdx.x & 127, w = tid >> 6, lane = tid & 63;
+    const int nx = active ? I.nx : 0;
+    const long long plane = active ? (long long)nx * I.ny : 0;
+    const int i0 = tid * L;
+    const int len = max(0, min(L, nx - i0));
+    cx<R> *rowp = active ? psi + (long long)row * nx : psi;
+    cx<R> v[3][L];
+#pragma unroll
+    for (int t = 0; t < L; ++t)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v[j][t] = t < len ? rowp[j * plane + i0 + t] : czero<R>();
+    if (active) {
+        R d0 = R(1), d1 = R(1), d2 = R(1);
+        if (dscale) {
+            d0 = R(coherent_load(dscale + 0));
+            d1 = R(coherent_load(dscale + 1));
+            d2 = R(coherent_load(dscale + 2));
+        }
+        const R yv = I.y0 + R(row) * I.dy;
+        const R vy = R(0.5) * I.m.kappa2 * yv * yv;
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            if (t < len) {
+                if (dscale) {
+                    v[0][t] = d0 * v[0][t];
+                    v[1][t] = d1 * v[1][t];
+                    v[2][t] = d2 * v[2][t];
+                }
+                const R xv = I.x0 + R(i0 + t) * I.dx;
+                pointwise(v[0][t], v[1][t], v[2][t], R(0.5) * xv * xv + vy, I.m);
+            }
+        }
+    }
+    auto publish = [&](const cx<R> (&x)[3][L], int round) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (lane == 0) P.E[round][w][0][j] = x[j][0];
+            if (lane == 63) P.E[round][w][1][j] = x[j][L - 1];
+        }
+    };
+    auto outer = [&](const cx<R> (&x)[L], int round, int j, cx<R> &before, cx<R> &after) {
+        before = ror1(x[L - 1]);
+        after = rol1(x[0]);
+        if (lane == 0) before = w > 0 ? P.E[round][0][1][j] : czero<R>();
+        if (lane == 63) after = w < 1 ? P.E[round][1][0][j] : czero<R>();
+    };
+    // SO update
+    publish(v, 0);
+    __syncthreads();
+    cx<R> u[3][L];
+    {
+        cx<R> vb[3], va[3];
+#pragma unroll
+        for (int jp = 0; jp < 3; ++jp) outer(v[jp], 0, jp, vb[jp], va[jp]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int t = 0; t < L; ++t) u[j][t] = v[j][t];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int jp = 0; jp < 3; ++jp)
+                if (I.qxmask & (1u << (3 * j + jp))) {
+                    const cx<R> q = I.qx[3 * j + jp];
+#pragma unroll
+                    for (int t = 0; t < L; ++t) {
+                        const cx<R> pv = t > 0 ? v[jp][t > 0 ? t - 1 : 0] : vb[jp];
+                        const cx<R> nv = t + 1 < L ? v[jp][t + 1 < L ? t + 1 : 0] : va[jp];
+                        u[j][t] = cfma(q, nv - pv, u[j][t]);
+                    }
+                }
+#pragma unroll
+        for (int t = 0; t < L; ++t)
+            if (t >= len)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) u[j][t] = czero<R>();
+    }
+    // right-hand side
+    publish(u, 1);
+    __syncthreads();
+    cx<R> r[3][L];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        cx<R> ub, ua;
+        outer(u[j], 1, j, ub, ua);
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            const cx<R> pu = t > 0 ? u[j][t > 0 ? t - 1 : 0] : ub;
+            const cx<R> nu = t + 1 < L ? u[j][t + 1 < L ? t + 1 : 0] : ua;
+            r[j][t] = t < len ? cn_rhs(I.rdx, u[j][t], pu + nu) : czero<R>();
+        }
+    }
+    // elimination in 128 chunks of 4 points
+    const ChunkCoef<R, L, 0> cpl(I.lx, active ? i0 : 0);
+    cx<R> Ak = mk(R(1), R(0));
+#pragma unroll
+    for (int t = 0; t < L; ++t)
+        if (t < len) Ak = Ak * (czero<R>() - cpl[t]);
+    cx<R> A[3], B[3], carry[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        A[j] = Ak;
+        B[j] = fwd_local<R, L>(r[j], len, cpl);
+    }
+    wave_scan_up3<R>(A, B, I.lv4);
+    if (lane == 63)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            P.scA[0][w][j] = A[j];
+            P.scB[0][w][j] = B[j];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        carry[j] = w > 0 ? P.scB[0][0][j] : czero<R>();
+        const cx<R> prev = shfl_up(cfma(A[j], carry[j], B[j]), 1);
+        if (lane >= 1) carry[j] = prev;
+    }
+    fwd_fix3<R, L, 0>(r, len, cpl, carry);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        A[j] = Ak;
+        B[j] = bwd_local<R, L>(r[j], len, cpl);
+    }
+    wave_scan_down3<R>(A, B, I.lv4);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            P.scA[1][w][j] = A[j];
+            P.scB[1][w][j] = B[j];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        carry[j] = w < 1 ? P.scB[1][1][j] : czero<R>();
+        const cx<R> next = shfl_down(cfma(A[j], carry[j], B[j]), 1);
+        if (lane < 63) carry[j] = next;
+    }
+    bwd_fix3<R, L, 0>(r, len, cpl, carry);
+    // coalesced stores through this wavefront's LDS line
+    cx<R> c0[L], c1[L], c2[L];
+    wave_exchange<R, L>(line, lane, r[0], c0);
+    wave_exchange<R, L>(line, lane, r[1], c1);
+    wave_exchange<R, L>(line, lane, r[2], c2);
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const int i = 64 * L * w + 64 * k + lane;
+            if (i < nx) {
+                put2(rowp + i, c0[k]);
+                put2(rowp + plane + i, c1[k]);
+                put2(rowp + 2 * plane + i, c2[k]);
+            }
+        }
+    }
+    __syncthreads();  // the LDS of the pair is reused by its next row
+}
+
+template <typename R>
+__device__ __forceinline__ void batch_x_item_pair(const BatchArgs<R> &a, int q, bool apply_renorm, cx<R> *line,
+                                                  PairSmem<R> &P) {
+    const bool active = q < a.nrows2;
+    const int it = active ? a.x_items[q] : 0;
+    const int inst = it >> 10, row = it & 1023;
+    const BatchInst<R> &I = a.inst[active ? inst : 0];
+    cx<R> *psi = a.pool + I.off;
+    const double *ds = apply_renorm && active ? a.renorm + (long long)inst * 8 : nullptr;
+    batch_xrow_pair<R>(I, psi, row, ds, line, P, active);
+}
+
 // x item of one wavefront (row q of the work list).
 template <typename R>
 __device__ __forceinline__ void batch_x_item_wave(const BatchArgs<R> &a, int q, bool apply_renorm, cx<R> *line) {
@@ -265,7 +456,10 @@ __device__ __forceinline__ void batch_x_item_wave(const BatchArgs<R> &a, int q, 
     case 1: batch_xrow_wave<R, 1>(I, psi, row, ds, line); break;
     case 2: batch_xrow_wave<R, 2>(I, psi, row, ds, line); break;
     case 4: batch_xrow_wave<R, 4>(I, psi, row, ds, line); break;
-    default: batch_xrow_wave<R, 8>(I, psi, row, ds, line); break;
+    default:
+        // (rows of 8-point chunks go to batch_xrow_pair where batch_pair_rows)
+        if constexpr (!batch_pair_rows<R>()) batch_xrow_wave<R, 8>(I, psi, row, ds, line);
+        break;
     }
 }
 
@@ -439,10 +633,15 @@ template <typename R>
 __global__ void __launch_bounds__(BATCH_THREADS) batch_persistent_kernel(BatchArgs<R> a) {
     __shared__ BatchSmem<R> S;
     __shared__ cx<R> xlines[BATCH_THREADS / 64][bx_line_slots<R, BATCH_MAX_LX>()];
-    const int wave = threadIdx.x >> 6;
+    __shared__ PairSmem<R> pairs[BATCH_THREADS / 128];
+    const int wave = threadIdx.x >> 6, pair = threadIdx.x >> 7;
     for (int step = 0; step < a.nsteps; ++step) {
-        // x rows, one per wavefront
-        for (int q = blockIdx.x * (BATCH_THREADS / 64) + wave; q < a.nrows; q += gridDim.x * (BATCH_THREADS / 64))
+        // x rows by two wavefronts (every pair runs the same number of rounds)
+        for (int q0 = blockIdx.x * (BATCH_THREADS / 128); q0 < a.nrows2; q0 += gridDim.x * (BATCH_THREADS / 128))
+            batch_x_item_pair(a, q0 + pair, step > 0, xlines[wave], pairs[pair]);
+        // the other x rows, one per wavefront
+        for (int q = a.nrows2 + blockIdx.x * (BATCH_THREADS / 64) + wave; q < a.nrows;
+             q += gridDim.x * (BATCH_THREADS / 64))
             batch_x_item_wave(a, q, step > 0, xlines[wave]);
         if (!grid_sync(a.bar, a.spin_limit)) return;
         for (int q = blockIdx.x; q < a.nyitems; q += gridDim.x) batch_y_item(a, q, S);
@@ -461,8 +660,16 @@ template <typename R>
 __global__ void __launch_bounds__(64 * BATCH_XWAVES) batch_x_kernel(BatchArgs<R> a, int apply_renorm) {
     __shared__ cx<R> xlines[BATCH_XWAVES][bx_line_slots<R, BATCH_MAX_LX>()];
     const int wave = threadIdx.x >> 6;
-    const int q = blockIdx.x * BATCH_XWAVES + wave;
+    const int q = a.nrows2 + blockIdx.x * BATCH_XWAVES + wave;
     if (q < a.nrows) batch_x_item_wave(a, q, apply_renorm != 0, xlines[wave]);
+}
+
+// The rows by two wavefronts: one row per workgroup of 128 threads.
+template <typename R>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) batch_x2_kernel(BatchArgs<R> a, int apply_renorm) {
+    __shared__ cx<R> xlines[2][bx_line_slots<R, 4>()];
+    __shared__ PairSmem<R> P;
+    batch_x_item_pair(a, blockIdx.x, apply_renorm != 0, xlines[threadIdx.x >> 6], P);
 }
 
 template <typename R>
