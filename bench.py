@@ -391,6 +391,10 @@ def batch_compare(steps: int = 200, warmup: int = 20):
     return out
 
 
+def progress(msg: str) -> None:
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -471,6 +475,7 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     obs_log = g.obs_log_read()
+    progress(f"timed {K} steps: {1e3 * el / K:.4f} ms/step")
 
     # kernel times: a separate window after the timed one, HIP start/stop
     # events attached to the x-pass and y-pass launches of every 7th step
@@ -519,19 +524,26 @@ def main():
         "observable_samples": len(obs_log),
         "final_observables": {k: obs_log[-1][k] for k in ("N", "M", "E", "rms")},
     }
+    progress("kernel timing window and copy ceiling done")
     if not args.no_adjoint and args.dtype == "f64":
         line["adjoint_cost_ratio"] = adjoint_ratio()
+        progress("adjoint cost ratio done")
     if not args.no_uso and args.dtype == "f64":
         line["unitary_so"] = unitary_so()
         line["strang_step"] = strang_step()
         line["rashba_step"] = rashba_step()
+        progress("unitary-SO, Strang and Rashba legs done")
     if not args.no_batch and args.dtype == "f64":
         line["complex64_step"] = complex64_step()
+        progress("complex64 leg done")
     if not args.no_batch:
         line["batch_c4"] = batch_compare()
+        progress("batch leg done")
         line["imag_workloads"] = imag_workloads()
+        progress("imaginary-time workloads done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, psi0, args.cpu_seconds)
+        progress("CPU baseline done")
     print(json.dumps(line), flush=True)
     g.close()
 
