@@ -276,9 +276,10 @@ def strang_step(steps: int = 1000, warmup: int = 50, every: int = 7):
 
 def rashba_step(steps: int = 1000, warmup: int = 50, every: int = 7):
     """The 1024^2 real-time workload with the Rashba coupling (y derivatives
-    in the SO term: a pointwise pass into a scratch copy, then the x-pass
-    variant that reads rows iy +- 1, then the y-pass): step rate and the
-    x-pass and y-pass kernel times (HIP events on every `every`-th step)."""
+    in the SO term: the pointwise sub-steps and the SO update over 2D tiles
+    into a scratch buffer, the x-pass with CN_x alone, the y-pass): step rate
+    and the x-pass and y-pass kernel times (HIP events on every `every`-th
+    step)."""
     import torch
 
     from paper_2009_13507_amd import api

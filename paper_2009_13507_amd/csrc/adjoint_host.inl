@@ -38,7 +38,7 @@ static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps)
         a.cx_ = T.x[MODE_ADJ].coef();
         a.rdiag = T.x[MODE_ADJ].rdiag;
         XArgs<R> tmp{};
-        fill_so(tmp, *g, MODE_ADJ);
+        fill_so<R>(tmp, *g, MODE_ADJ);
         for (int q = 0; q < 9; ++q) a.qx[q] = tmp.qx[q];
         a.qxmask = tmp.qxmask;
         a.omega_partials = g->adj_partials.as<double>();

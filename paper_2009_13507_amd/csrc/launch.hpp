@@ -40,6 +40,7 @@ template <typename R> hipError_t launch_ypass(const Launch &c, const YArgs<R> &a
 template <typename R> hipError_t launch_step1d(const Launch &c, const Args1D<R> &a, int L);
 template <typename R> hipError_t launch_adj_xpass(const Launch &c, const AdjXArgs<R> &a, int L, int rows);
 template <typename R> hipError_t launch_pointwise(const Launch &c, const PArgs<R> &a, int blocks);
+template <typename R> hipError_t launch_pso(const Launch &c, const SOArgs<R> &a);
 template <typename R> hipError_t launch_scale(const Launch &c, cx<R> *psi, long long plane, const double *d, int blocks);
 template <typename R> hipError_t launch_obs(const Launch &c, const ObsArgs<R> &a, int blocks);
 hipError_t launch_renorm_finalize(const Launch &c, const double *partials, int ntiles, RenormSpec sp, double *out);

@@ -16,6 +16,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ssgp.h"
@@ -526,19 +527,21 @@ static int launch_y(const GridCore &g, const YArgs<R> &a, const YShape &ys, hipE
     return SSGP_OK;
 }
 
-template <typename R>
-static void fill_so(XArgs<R> &a, const GridCore &g, int mode) {
+// SO update psi' = psi - k dt H_SO psi with central differences: the
+// coefficients of psi_j'(i+1) - psi_j'(i-1) along x, and along y for the
+// argument blocks that carry them (SOArgs).
+template <typename R, typename A>
+static void fill_so(A &a, const GridCore &g, int mode) {
     const SOForm f = so_form(g.p.so, g.p.gamma);
     const cd k = kfac(mode);
-    // psi' = psi - k dt H psi with central differences
     cd kd = k * g.p.dt;
     if (mode == MODE_ADJ) kd = -kd;  // S^H = I + i dt H in real time
-    for (int q = 0; q < 9; ++q) {
-        a.qx[q] = tor<R>(-kd * f.hx[q] / (2.0 * g.dx));
-        a.qy[q] = tor<R>(-kd * f.hy[q] / (2.0 * g.dy));
-    }
+    for (int q = 0; q < 9; ++q) a.qx[q] = tor<R>(-kd * f.hx[q] / (2.0 * g.dx));
     a.qxmask = g.p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hx);
-    a.qymask = g.p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hy);
+    if constexpr (std::is_same<A, SOArgs<R>>::value) {
+        for (int q = 0; q < 9; ++q) a.qy[q] = tor<R>(-kd * f.hy[q] / (2.0 * g.dy));
+        a.qymask = g.p.so == SSGP_SO_NONE ? 0u : nz_mask(f.hy);
+    }
 }
 
 template <typename R>
@@ -559,8 +562,7 @@ static XArgs<R> x_args(ssgp_grid g, int mode, const void *src, void *dst, double
     a.pointwise = 1;
     a.cx_ = T.xb[mode].coef();
     a.rdiag = T.x[mode].rdiag;
-    fill_so(a, *g, mode);
-    a.so_y = 0;
+    fill_so<R>(a, *g, mode);
     a.ramp = nullptr;
     if (g->scheme != SSGP_SCHEME_PAPER && g->dim == 2 && mode != MODE_ADJ) {
         a.strang = g->scheme == SSGP_SCHEME_STRANG ? 1 : 0;
@@ -622,7 +624,6 @@ template <typename R>
 static int strang_close(ssgp_grid g, int mode, void *psi, double omega, double *partials) {
     PArgs<R> pa{};
     pa.psi = static_cast<cx<R> *>(psi);
-    pa.src = nullptr;
     pa.nx = g->nx;
     pa.ny = g->ny;
     pa.plane = plane_of(*g);
@@ -633,7 +634,6 @@ static int strang_close(ssgp_grid g, int mode, void *psi, double omega, double *
     pa.m = model<R>(*g, mode, omega);
     pa.m.dt = (R)(0.5 * g->p.dt);
     pa.dscale = nullptr;
-    pa.p2 = 1;
     pa.norm_partials = partials;
     LAUNCH_TRY(launch_pointwise<R>(lc(*g), pa, ew_blocks(pa.plane)));
     return SSGP_OK;
@@ -658,30 +658,33 @@ static int step2d(ssgp_grid g, int mode, const void *src, void *dst, double omeg
     const YShape ys = y_shape(g->ny);
     const int rtiles = renorm_tiles(*g);
     if (so_y_terms(g->p.so) && g->p.gamma != 0.0) {
-        // pointwise pass from src into scratch, then SO(x,y) + CN_x from scratch
+        // RENORM scale, CALCNU, HERM and SO(x, y) from src into scratch, then
+        // CN_x from scratch into dst
         const size_t bytes = (size_t)3 * plane_of(*g) * sizeof(cx<R>);
         SSGP_TRY(g->scratch.ensure(bytes));
-        PArgs<R> pa{};
-        pa.psi = g->scratch.as<cx<R>>();
-        pa.src = src == g->scratch.p ? nullptr : static_cast<const cx<R> *>(src);
-        pa.nx = g->nx;
-        pa.ny = g->ny;
-        pa.plane = plane_of(*g);
-        pa.dx = (R)g->dx;
-        pa.dy = (R)g->dy;
-        pa.x0 = (R)(-0.5 * g->nx * g->dx);
-        pa.y0 = (R)(-0.5 * g->ny * g->dy);
-        pa.m = model<R>(*g, mode, omega);
-        pa.dscale = nullptr;
+        if (src == g->scratch.p) return fail(SSGP_EINVAL, "the state is the scratch buffer");
+        XArgs<R> xa = x_args<R>(g, mode, g->scratch.p, dst, omega, nullptr);
+        SOArgs<R> sa{};
+        sa.src = static_cast<const cx<R> *>(src);
+        sa.dst = g->scratch.as<cx<R>>();
+        sa.nx = g->nx;
+        sa.ny = g->ny;
+        sa.plane = plane_of(*g);
+        sa.dx = (R)g->dx;
+        sa.dy = (R)g->dy;
+        sa.x0 = (R)(-0.5 * g->nx * g->dx);
+        sa.y0 = (R)(-0.5 * g->ny * g->dy);
+        sa.m = xa.m;
+        sa.dscale = nullptr;
+        fill_so<R>(sa, *g, mode);
         if (renorm_prev) {
             LAUNCH_TRY(launch_renorm_finalize(lc(*g), g->partials.as<double>(), rtiles, renorm_spec(*g),
                                               g->renorm.as<double>()));
-            pa.dscale = g->renorm.as<double>();
+            sa.dscale = g->renorm.as<double>();
         }
-        LAUNCH_TRY(launch_pointwise<R>(lc(*g), pa, ew_blocks(pa.plane)));
-        XArgs<R> xa = x_args<R>(g, mode, g->scratch.p, dst, omega, nullptr);
+        LAUNCH_TRY(launch_pso<R>(lc(*g), sa));
         xa.pointwise = 0;
-        xa.so_y = 1;
+        xa.qxmask = 0;  // (the SO update is in the state read)
         SSGP_TRY(launch_x<R>(*g, xa, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     } else {
         XArgs<R> xa = x_args<R>(g, mode, src, dst, omega, nullptr);
@@ -789,7 +792,7 @@ template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int
     a.cx_ = T.x[mode].coef();
     a.rdiag = T.x[mode].rdiag;
     XArgs<R> tmp{};
-    fill_so(tmp, *g, mode);
+    fill_so<R>(tmp, *g, mode);
     for (int q = 0; q < 9; ++q) a.qx[q] = tmp.qx[q];
     a.qxmask = tmp.qxmask;
     a.sp = renorm_spec(*g);

@@ -582,7 +582,7 @@ __device__ __forceinline__ void renorm_factors(const RenormSpec &sp, const doubl
 
 template <typename R> struct XArgs {
     const cx<R> *src;          // state read (3 planes)
-    cx<R> *dst;                // state written (may equal src unless so_y)
+    cx<R> *dst;                // state written (may equal src)
     int nx, ny;
     long long plane;           // nx * ny
     R dx, dy, x0, y0;
@@ -597,9 +597,6 @@ template <typename R> struct XArgs {
     cx<R> rdiag;               // diagonal of (I - sT)/o (off-diagonal -1)
     cx<R> qx[9];               // SO: psi'_j += sum_j' qx[j][j'] (psi_j'(i+1) - psi_j'(i-1))
     unsigned qxmask;           // bit 3j+j' set where qx[j][j'] != 0
-    int so_y;                  // 1: add qy terms with rows iy +- 1 of src
-    cx<R> qy[9];
-    unsigned qymask;
     // Unitary-SO scheme (x-derivative SO forms; no qx terms then): the SO
     // term is solved together with CN_x.  In the eigenbasis of the SO spin
     // matrix (columns of rot, row-major rot[3 j + c]) component c is a
@@ -698,8 +695,9 @@ __device__ __forceinline__ void wave_scan_down3(cx<R> (&A)[3], cx<R> (&B)[3], in
 // components (three independent recurrences), the chunk maps are scanned
 // within each wavefront and carried across the 4 wavefronts through LDS, and
 // each thread applies its carry fix-ups and stores its points.  FULL: the
-// row has exactly 256 KM points, so no point needs a range check.  SOY: the
-// SO form has y derivatives (terms with rows iy +- 1 of src).
+// row has exactly 256 KM points, so no point needs a range check.  (The SO
+// forms with y derivatives come here with their SO update already applied,
+// from pso_kernel, and no SO terms.)
 template <typename R, int KM> struct XShared {
     double red[3][XPASS_THREADS];      // RENORM reduction of the tile partials
     double d[3];                       // RENORM factors
@@ -780,7 +778,7 @@ __device__ __forceinline__ void store_row(cx<R> *dst, long long plane, int nx, c
 
 // Everything after the loads, for one row whose KM points per thread are in
 // v (zero beyond nx).
-template <typename R, int KM, int CM, bool FULL, bool SOY, bool USO, bool P2>
+template <typename R, int KM, int CM, bool FULL, bool USO, bool P2>
 __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)[3][KM], XShared<R, KM> &sh) {
     cx<R> *E = sh.E;
     auto &scA = sh.scA;
@@ -789,7 +787,6 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int i0 = tid * KM;  // this thread's points: i0 .. i0 + KM - 1
     const long long roff = (long long)row * nx;
-    const cx<R> *src = a.src + roff;
 
     // ---- RENORM scale, CALCNU + HERM
     if (a.rpart) {
@@ -884,7 +881,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         if (lane == 63) after = w < 3 ? Er[((w + 1) * 2 + 0) * 3 + j] : czero<R>();
     };
 
-    // ---- SO update u = v + q (v(i+1) - v(i-1)) [+ y-derivative terms]
+    // ---- SO update u = v + q (v(i+1) - v(i-1))
     exchange_edges(v, 0);
     __syncthreads();
     cx<R> u[3][KM];
@@ -912,27 +909,10 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
                     }
                 }
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int i = i0 + k;
-            const bool ok = FULL || i < nx;
-            if (!ok) {
+        for (int k = 0; k < KM; ++k)
+            if (!FULL && i0 + k >= nx)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) u[j][k] = czero<R>();
-            }
-            if (SOY && ok) {
-                cx<R> up[3], dn[3];
-#pragma unroll
-                for (int jp = 0; jp < 3; ++jp) {
-                    up[jp] = row + 1 < a.ny ? src[jp * a.plane + nx + i] : czero<R>();
-                    dn[jp] = row >= 1 ? src[jp * a.plane - nx + i] : czero<R>();
-                }
-#pragma unroll
-                for (int j = 0; j < 3; ++j)
-#pragma unroll
-                    for (int jp = 0; jp < 3; ++jp)
-                        if (a.qymask & (1u << (3 * j + jp))) u[j][k] = cfma(a.qy[3 * j + jp], up[jp] - dn[jp], u[j][k]);
-            }
-        }
     }
 
     // ---- right-hand side (I - sT) u / o
@@ -1058,14 +1038,12 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
 // per-lane tables (CM = 0), or from 8 points per thread on, it takes the
 // registers of 2 wavefronts per SIMD; with 4 points and tabulated fix-ups it
 // keeps 4, which measured faster at 1024^2 than 2 without register spills:
-// 36.6 against 39.4 us.  The y-derivative SO form at 4 points per thread
-// spills at 4 wavefronts per SIMD and runs faster at 2: 42.2 against 54.3 us
-// at 1024^2.)
-template <typename R, int KM, int CM, bool FULL, bool SOY, bool USO = false, bool P2 = false>
+// 36.6 against 39.4 us.)
+template <typename R, int KM, int CM, bool FULL, bool USO = false, bool P2 = false>
 __global__ void __launch_bounds__(XPASS_THREADS)
 __attribute__((amdgpu_waves_per_eu(P2 ? (KM <= 4 ? 2 : 1)
                                    : USO ? (KM <= 1 || (KM <= 4 && CM != 0) ? 4 : 2)
-                                         : (KM <= 4 ? (SOY && KM == 4 ? 2 : 4) : 1))))
+                                         : (KM <= 4 ? 4 : 1))))
 xpass_kernel(XArgs<R> a) {
     __shared__ XShared<R, KM> sh;
     const int nx = FULL ? XPASS_THREADS * KM : a.nx;
@@ -1079,7 +1057,7 @@ xpass_kernel(XArgs<R> a) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) v[j][k] = (FULL || i < nx) ? src[j * a.plane + i] : czero<R>();
     }
-    xpass_row<R, KM, CM, FULL, SOY, USO, P2>(a, row, v, sh);
+    xpass_row<R, KM, CM, FULL, USO, P2>(a, row, v, sh);
 }
 
 // ------------------------------------------------------------- y-pass ---
@@ -1221,53 +1199,45 @@ __global__ void __launch_bounds__(YPASS_MAX_THREADS) ypass_kernel(YArgs<R> a) {
     }
 }
 
-// ------------------------------------------------ pointwise-only pass ---
-// Used ahead of an x-pass that reads neighbouring rows (y-derivative SO):
-// RENORM scale, CALCNU and HERM, from src (or in place when src is null)
-// into psi.  With p2 set instead: the second-order stage P2 over m.dt (the
-// last stage of a step of the opt-in Strang scheme), and, with norm_partials,
-// each workgroup's sums of |psi_j|^2 of the result in
-// norm_partials[j * gridDim.x + block] (for the RENORM that follows).
+// -------------------------------------- second-order pointwise pass ---
+// The closing stage P2 over m.dt of a step of the opt-in Strang scheme
+// (after its y-pass), in place, from psi (RENORM factors dscale applied
+// first when given); with norm_partials, each workgroup's sums of |psi_j|^2
+// of the result in norm_partials[j * gridDim.x + block] (for the RENORM that
+// follows).
 template <typename R> struct PArgs {
     cx<R> *psi;
-    const cx<R> *src;
     int nx, ny;
     long long plane;
     R dx, dy, x0, y0;
     Model<R> m;
     const double *dscale;
-    int p2;
     double *norm_partials;
 };
 
-template <typename R, bool P2>
+template <typename R>
 __global__ void __launch_bounds__(256) pointwise_kernel(PArgs<R> a) {
     const long long n = a.plane;
     double nrm[3] = {0.0, 0.0, 0.0};
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x) {
         const int ix = (int)(q % a.nx), iy = (int)(q / a.nx);
-        const cx<R> *in = a.src ? a.src : a.psi;
-        cx<R> p = in[q], z = in[n + q], m = in[2 * n + q];
+        cx<R> p = a.psi[q], z = a.psi[n + q], m = a.psi[2 * n + q];
         if (a.dscale) {
             p = R(a.dscale[0]) * p;
             z = R(a.dscale[1]) * z;
             m = R(a.dscale[2]) * m;
         }
         const R xv = a.x0 + R(ix) * a.dx, yv = a.y0 + R(iy) * a.dy;
-        const R V = R(0.5) * (xv * xv + a.m.kappa2 * yv * yv);
-        if constexpr (P2) pointwise2(p, z, m, V, a.m);
-        else pointwise(p, z, m, V, a.m);
+        pointwise2(p, z, m, R(0.5) * (xv * xv + a.m.kappa2 * yv * yv), a.m);
         a.psi[q] = p;
         a.psi[n + q] = z;
         a.psi[2 * n + q] = m;
-        if constexpr (P2) {
-            nrm[0] += (double)abs2(p);
-            nrm[1] += (double)abs2(z);
-            nrm[2] += (double)abs2(m);
-        }
+        nrm[0] += (double)abs2(p);
+        nrm[1] += (double)abs2(z);
+        nrm[2] += (double)abs2(m);
     }
-    if (P2 && a.norm_partials) {
+    if (a.norm_partials) {
         __shared__ double red[3][4];
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -1281,6 +1251,148 @@ __global__ void __launch_bounds__(256) pointwise_kernel(PArgs<R> a) {
         if (threadIdx.x < 3) {
             const int j = threadIdx.x;
             a.norm_partials[(long long)j * gridDim.x + blockIdx.x] = red[j][0] + red[j][1] + red[j][2] + red[j][3];
+        }
+    }
+}
+
+// ------------------------------- pointwise + SO pass (y-derivative SO) ---
+// The SO update of the couplings with y derivatives (Rashba, Dresselhaus)
+// takes the neighbours of a point in y after their CALCNU and HERM, which a
+// row-per-workgroup x-pass does not hold.  This pass takes the state through
+// RENORM scale, CALCNU, HERM and the whole SO update psi - k dt H_SO psi
+// (central differences, zero ghosts beyond the grid; per point the x terms,
+// then the y terms, in the order of the x-pass) into a second buffer, and
+// the x-pass then runs CN_x on that buffer with neither.
+//
+// One workgroup per tile of 64 columns and PSO_TY = PSO_WAVES * PSO_RPW
+// rows: wavefront w owns PSO_RPW consecutive rows of the tile and lane l
+// column l.  x neighbours come from the adjacent lanes (DPP), y neighbours
+// from the wavefront's own registers or, for its first and last row, from
+// the adjacent wavefronts through LDS.  The pointwise values just outside
+// the tile are recomputed (halo): the row above by wavefront 0, the row
+// below by the last wavefront, the columns left and right by wavefront 1.
+template <typename R> struct SOArgs {
+    const cx<R> *src;          // state (read only)
+    cx<R> *dst;                // the state after SO (another buffer)
+    int nx, ny;
+    long long plane;
+    R dx, dy, x0, y0;
+    Model<R> m;
+    const double *dscale;      // RENORM factors to apply first, or nullptr
+    cx<R> qx[9], qy[9];        // as in XArgs
+    unsigned qxmask, qymask;
+};
+
+constexpr int PSO_WAVES = 8, PSO_RPW = 2;  // wavefronts, rows per wavefront
+constexpr int PSO_TX = 64, PSO_TY = PSO_WAVES * PSO_RPW;
+static_assert(PSO_WAVES >= 3 && 2 * PSO_TY <= 64, "halo roles: wavefronts 0, 1 and the last; a lane per column point");
+
+template <typename R> struct PsoShared {
+    cx<R> yrow[2 * PSO_WAVES + 2][3][PSO_TX];  // 0: the row above the tile; 2w + 1, 2w + 2: the first
+                                               // and last row of wavefront w; the last: the row below
+    cx<R> xcol[2][PSO_TY][3];                  // the columns left and right of the tile
+};
+
+// RENORM scale, CALCNU and HERM of a loaded point (V as in pointwise_kernel).
+template <typename R>
+__device__ __forceinline__ void pso_pointwise(const SOArgs<R> &a, int x, int y, cx<R> (&v)[3], R d0, R d1, R d2) {
+    v[0] = d0 * v[0];
+    v[1] = d1 * v[1];
+    v[2] = d2 * v[2];
+    const R xv = a.x0 + R(x) * a.dx, yv = a.y0 + R(y) * a.dy;
+    pointwise(v[0], v[1], v[2], R(0.5) * (xv * xv + a.m.kappa2 * yv * yv), a.m);
+}
+
+// FULL: the point is known to lie inside the grid.
+template <typename R, bool FULL>
+__device__ __forceinline__ void pso_load(const SOArgs<R> &a, int x, int y, cx<R> (&v)[3]) {
+    const bool in = FULL || (x >= 0 && x < a.nx && y >= 0 && y < a.ny);
+    const long long q = in ? (long long)y * a.nx + x : 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) v[j] = in ? a.src[j * a.plane + q] : czero<R>();
+}
+
+// FULL: every tile lies inside the grid (nx and ny multiples of the tile).
+template <typename R, bool FULL>
+__global__ void __launch_bounds__(64 * PSO_WAVES) __attribute__((amdgpu_waves_per_eu(4))) pso_kernel(SOArgs<R> a) {
+    __shared__ PsoShared<R> sh;
+    const int lane = threadIdx.x & 63;
+    // (w is uniform in the wavefront: the row offsets stay scalar)
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ntx = (a.nx + PSO_TX - 1) / PSO_TX;
+    const int x0 = (blockIdx.x % ntx) * PSO_TX, y0 = (blockIdx.x / ntx) * PSO_TY;
+    const int x = x0 + lane, yw = y0 + PSO_RPW * w;
+    R d0 = R(1), d1 = R(1), d2 = R(1);
+    if (a.dscale) {
+        d0 = R(a.dscale[0]);
+        d1 = R(a.dscale[1]);
+        d2 = R(a.dscale[2]);
+    }
+    // this wavefront's share of the halo first, straight into LDS (zero
+    // outside the grid: the pointwise sub-steps keep zero at zero)
+    {
+        int hx = x, hy = -1;  // the halo point of this lane (hy < 0: none)
+        if (w == 0) hy = y0 - 1;
+        else if (w == PSO_WAVES - 1) hy = y0 + PSO_TY;
+        else if (w == 1 && lane < 2 * PSO_TY) {
+            hx = lane < PSO_TY ? x0 - 1 : x0 + PSO_TX;
+            hy = y0 + (lane % PSO_TY);
+        }
+        cx<R> h[3];
+        pso_load<R, false>(a, hx, hy, h);
+        if (hy >= 0) pso_pointwise(a, hx, hy, h, d0, d1, d2);
+        if (w == 0)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) sh.yrow[0][j][lane] = h[j];
+        if (w == PSO_WAVES - 1)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) sh.yrow[2 * PSO_WAVES + 1][j][lane] = h[j];
+        if (w == 1 && lane < 2 * PSO_TY)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) sh.xcol[lane / PSO_TY][lane % PSO_TY][j] = h[j];
+    }
+    // the wavefront's rows; the first and last into LDS
+    cx<R> v[PSO_RPW][3];
+#pragma unroll
+    for (int k = 0; k < PSO_RPW; ++k) pso_load<R, FULL>(a, x, yw + k, v[k]);
+#pragma unroll
+    for (int k = 0; k < PSO_RPW; ++k) pso_pointwise(a, x, yw + k, v[k], d0, d1, d2);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        sh.yrow[2 * w + 1][j][lane] = v[0][j];
+        sh.yrow[2 * w + 2][j][lane] = v[PSO_RPW - 1][j];
+    }
+    __syncthreads();
+    // SO update and stores
+#pragma unroll
+    for (int k = 0; k < PSO_RPW; ++k) {
+        cx<R> pv[3], nv[3], dn[3], up[3], u[3];
+#pragma unroll
+        for (int jp = 0; jp < 3; ++jp) {
+            pv[jp] = ror1(v[k][jp]);
+            nv[jp] = rol1(v[k][jp]);
+            if (lane == 0) pv[jp] = sh.xcol[0][PSO_RPW * w + k][jp];
+            if (lane == 63) nv[jp] = sh.xcol[1][PSO_RPW * w + k][jp];
+            dn[jp] = k > 0 ? v[k > 0 ? k - 1 : 0][jp] : sh.yrow[2 * w][jp][lane];
+            up[jp] = k < PSO_RPW - 1 ? v[k < PSO_RPW - 1 ? k + 1 : 0][jp] : sh.yrow[2 * w + 3][jp][lane];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            u[j] = v[k][j];
+#pragma unroll
+            for (int jp = 0; jp < 3; ++jp)
+                if (a.qxmask & (1u << (3 * j + jp))) u[j] = cfma(a.qx[3 * j + jp], nv[jp] - pv[jp], u[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int jp = 0; jp < 3; ++jp)
+                if (a.qymask & (1u << (3 * j + jp))) u[j] = cfma(a.qy[3 * j + jp], up[jp] - dn[jp], u[j]);
+        const int y = yw + k;
+        if (FULL || (x < a.nx && y < a.ny)) {
+            const long long q = (long long)y * a.nx + x;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) a.dst[j * a.plane + q] = u[j];
         }
     }
 }
