@@ -9,25 +9,15 @@
 
 namespace ssgp {
 
-// Sums the per-tile |psi|^2 partials (fixed order) and writes
-// out = {d_+1, d_0, d_-1, N_+1, N_0, N_-1, fallback}.
-__global__ void __launch_bounds__(256) renorm_finalize_kernel(const double *partials, int ntiles,
-                                                              RenormSpec sp, double *out) {
-    __shared__ double red[3][256];
-    const int t = threadIdx.x;
-    for (int j = 0; j < 3; ++j) {
-        double s = 0.0;
-        for (int q = t; q < ntiles; q += 256) s += partials[(long long)j * ntiles + q];
-        red[j][t] = s;
-    }
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (t < w)
-            for (int j = 0; j < 3; ++j) red[j][t] += red[j][t + w];
-        __syncthreads();
-    }
-    if (t == 0) {
-        double N[3] = {red[0][0] * sp.dA, red[1][0] * sp.dA, red[2][0] * sp.dA};
+// Sums the per-tile |psi|^2 partials (wave_tile_sums: the order every
+// x-pass workgroup uses too) and writes
+// out = {d_+1, d_0, d_-1, N_+1, N_0, N_-1, fallback}.  One wavefront.
+__global__ void __launch_bounds__(64) renorm_finalize_kernel(const double *partials, int ntiles, RenormSpec sp,
+                                                             double *out) {
+    double s[3];
+    wave_tile_sums(partials, ntiles, s);
+    if (threadIdx.x == 0) {
+        double N[3] = {s[0] * sp.dA, s[1] * sp.dA, s[2] * sp.dA};
         double d[3], fb = 0.0;
         renorm_factors(sp, N, d, &fb);
         for (int j = 0; j < 3; ++j) {

@@ -580,6 +580,25 @@ __device__ __forceinline__ void renorm_factors(const RenormSpec &sp, const doubl
     d[0] = d[1] = d[2] = dd;
 }
 
+// Sums of per-tile |psi_j|^2 partials, stored [3][ntiles], by one whole
+// wavefront in a fixed order: lane l adds tiles l, l + 64, l + 128, ... in
+// turn, then the 64 lane sums are added pairwise (offsets 32, 16, ..., 1).
+// Every caller (the finalize kernel, each x-pass workgroup) gets the same
+// bits; the sums are in lane 0.
+__device__ __forceinline__ void wave_tile_sums(const double *partials, int ntiles, double (&s)[3]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        double t = 0.0;
+        for (int q = lane; q < ntiles; q += 64) t += partials[(long long)j * ntiles + q];
+        s[j] = t;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s[j] += __shfl_down(s[j], d, 64);
+}
+
 template <typename R> struct XArgs {
     const cx<R> *src;          // state read (3 planes)
     cx<R> *dst;                // state written (may equal src)
@@ -699,7 +718,6 @@ __device__ __forceinline__ void wave_scan_down3(cx<R> (&A)[3], cx<R> (&B)[3], in
 // forms with y derivatives come here with their SO update already applied,
 // from pso_kernel, and no SO terms.)
 template <typename R, int KM> struct XShared {
-    double red[3][XPASS_THREADS];      // RENORM reduction of the tile partials
     double d[3];                       // RENORM factors
     cx<R> E[2 * 24];                   // edges: [round][4 waves][2 ends][3 comps]
     cx<R> scA[2][4][3], scB[2][4][3];  // wavefront maps: [sweep][wave][comp]
@@ -789,26 +807,18 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     const long long roff = (long long)row * nx;
 
     // ---- RENORM scale, CALCNU + HERM
-    if (a.rpart) {
+    if (__builtin_expect(a.rpart != nullptr, 0)) {  // (measured: the layout keeps the real-time pass as fast)
         // the factors from the previous step's tile partials: the same
         // fixed-order sums as renorm_finalize_kernel, in every workgroup
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            double t = 0.0;
-            for (int q = tid; q < a.rntiles; q += XPASS_THREADS) t += a.rpart[(long long)j * a.rntiles + q];
-            sh.red[j][tid] = t;
-        }
-        __syncthreads();
-        for (int wd = XPASS_THREADS / 2; wd >= 1; wd >>= 1) {
-            if (tid < wd)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) sh.red[j][tid] += sh.red[j][tid + wd];
-            __syncthreads();
-        }
-        if (tid == 0) {
-            const double N[3] = {sh.red[0][0] * a.rsp.dA, sh.red[1][0] * a.rsp.dA, sh.red[2][0] * a.rsp.dA};
-            double fb = 0.0;
-            renorm_factors(a.rsp, N, sh.d, &fb);
+        // (wavefront 0; the others' loads are in flight meanwhile)
+        if (w == 0) {
+            double sum[3];
+            wave_tile_sums(a.rpart, a.rntiles, sum);
+            if (lane == 0) {
+                const double N[3] = {sum[0] * a.rsp.dA, sum[1] * a.rsp.dA, sum[2] * a.rsp.dA};
+                double fb = 0.0;
+                renorm_factors(a.rsp, N, sh.d, &fb);
+            }
         }
         __syncthreads();
     }

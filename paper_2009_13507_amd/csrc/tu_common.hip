@@ -5,7 +5,7 @@
 namespace ssgp {
 
 hipError_t launch_renorm_finalize(const Launch &c, const double *partials, int ntiles, RenormSpec sp, double *out) {
-    renorm_finalize_kernel<<<1, 256, 0, c.stream>>>(partials, ntiles, sp, out);
+    renorm_finalize_kernel<<<1, 64, 0, c.stream>>>(partials, ntiles, sp, out);
     return hipGetLastError();
 }
 
