@@ -325,7 +325,8 @@ struct GridCore {
     std::vector<StepGraph> graphs;
     hipStream_t cap = nullptr;
     int scheme = SSGP_SCHEME_PAPER;
-    cd uso_rot[9];  // unitary-SO scheme: eigenvectors of the SO spin matrix (columns)
+    double uso_wr[9];  // unitary-SO scheme: eigenvectors of the SO spin matrix (columns),
+    int uso_p[3];      // as diag(i^uso_p[j]) uso_wr
     bool renorm_real = false;  // RENORM after every real-time step as well
     // steps of this mode end with the RENORM rule
     bool renorms(int mode) const { return mode == MODE_IMAG || (mode == MODE_REAL && renorm_real); }
@@ -347,7 +348,7 @@ template <typename R> struct Tables {
     CNDev<R> xb[NMODES];  // x lines as 256 chunks (2D x-pass)
     CNDev<R> y[NMODES];
     CNDev<R> xu[NMODES][3];  // unitary-SO scheme: the three symmetrised lines (as x in
-    DevBuf ramp[NMODES];     //   1D, as xb in 2D) and their phase ramps [3][nx]
+    DevBuf ramp[NMODES];     //   1D, as xb in 2D) and the phase ramp of line 0 [nx]
 };
 
 struct ssgp_grid_s : GridCore {
@@ -419,27 +420,49 @@ template <typename R> static int build_uso(ssgp_grid g, int mode, int L, int nch
             for (int c = 0; c < 3; ++c) m += W[3 * j + c] * lam[c] * std::conj(W[3 * k + c]);
             if (std::abs(m - S[3 * j + k]) > 1e-15) return fail(SSGP_EDEVICE, "spin eigenvectors inconsistent");
         }
-    for (int q = 0; q < 9; ++q) g->uso_rot[q] = W[q];
+    // W = diag(i^p_j) Wr with Wr real: the kernels rotate with real numbers
+    const cd ipow[4] = {cd(1.0, 0.0), cd(0.0, 1.0), cd(-1.0, 0.0), cd(0.0, -1.0)};
+    for (int j = 0; j < 3; ++j) {
+        int p = -1;
+        for (int k = 0; k < 4 && p < 0; ++k) {
+            const cd ph = ipow[k];
+            bool ok = true;
+            for (int c = 0; c < 3; ++c) ok = ok && std::abs(std::imag(std::conj(ph) * W[3 * j + c])) < 1e-15;
+            if (ok) p = k;
+        }
+        if (p < 0) return fail(SSGP_EDEVICE, "spin eigenvectors: row %d is not a phase times a real row", j);
+        g->uso_p[j] = p;
+        for (int c = 0; c < 3; ++c) g->uso_wr[3 * j + c] = std::real(std::conj(ipow[p]) * W[3 * j + c]);
+    }
+    // the eigenvalues are (lambda, 0, -lambda): line 1 has no drift and line
+    // 2's ramp is the conjugate of line 0's (the kernels rely on both)
+    if (lam[1] != 0.0 || lam[2] != -lam[0]) return fail(SSGP_EDEVICE, "spin eigenvalues not (l, 0, -l)");
     const double h = g->dx, gam = erd ? -g->p.gamma : g->p.gamma;
     const cd s = cn_s(mode, g->p.dt), I(0.0, 1.0);
     const cd d = 1.0 + s / (h * h);
     CNHost tab[3];
-    std::vector<cx<R>> ramp((size_t)3 * g->nx);
+    std::vector<cx<R>> ramp((size_t)g->nx);
     int levels = 1;
+    cd rho0 = 1.0;
     for (int c = 0; c < 3; ++c) {
         const cd u = s * (-0.5 / (h * h) - I * gam * lam[c] / (2.0 * h));
-        const cd l = s * (-0.5 / (h * h) + I * gam * lam[c] / (2.0 * h));
-        cd rho = std::sqrt(l / u);
-        rho /= std::abs(rho);
+        cd rho = 1.0;
+        if (c == 0) {
+            const cd l = s * (-0.5 / (h * h) + I * gam * lam[c] / (2.0 * h));
+            rho = std::sqrt(l / u);
+            rho /= std::abs(rho);
+            rho0 = rho;
+        } else if (c == 2) {
+            rho = std::conj(rho0);  // sqrt(l/u) of line 2 is the conjugate of line 0's
+        }
         const cd o = u * rho;
         if (!(std::abs(d) > 2.0 * std::abs(o)))
             return fail(SSGP_EINVAL, "unitary SO: the line matrix is not diagonally dominant (dt gamma too large)");
         tab[c] = cn_tables_do(g->nx, d, o, (2.0 - d) / o, L, nchunks, 6);
         levels = std::max(levels, tab[c].levels);
-        const double th = std::arg(rho);
-        for (int i = 0; i < g->nx; ++i)
-            ramp[(size_t)c * g->nx + i] = tor<R>(cd(std::cos(th * i), std::sin(th * i)));
     }
+    const double th = std::arg(rho0);
+    for (int i = 0; i < g->nx; ++i) ramp[(size_t)i] = tor<R>(cd(std::cos(th * i), std::sin(th * i)));
     for (int c = 0; c < 3; ++c) {
         tab[c].levels = levels;
         SSGP_TRY(upload_cn<R>(T.xu[mode][c], tab[c], g->nx, L, nchunks, g->stream));
@@ -567,7 +590,12 @@ static XArgs<R> x_args(ssgp_grid g, int mode, const void *src, void *dst, double
     if (g->scheme != SSGP_SCHEME_PAPER && g->dim == 2 && mode != MODE_ADJ) {
         a.strang = g->scheme == SSGP_SCHEME_STRANG ? 1 : 0;
         a.ramp = T.ramp[mode].template as<cx<R>>();
-        for (int q = 0; q < 9; ++q) a.rot[q] = tor<R>(g->uso_rot[q]);
+        for (int q = 0; q < 9; ++q) a.rotr[q] = (R)g->uso_wr[q];
+        a.rotphased = 0;
+        for (int j = 0; j < 3; ++j) {
+            a.rotp[j] = g->uso_p[j];
+            if (g->uso_p[j] != 0) a.rotphased = 1;
+        }
         for (int c = 0; c < 3; ++c) {
             a.cu[c] = T.xu[mode][c].coef();
             a.rdiag_u[c] = T.xu[mode][c].rdiag;
@@ -802,7 +830,12 @@ template <typename R> static int launch_1d(ssgp_grid g, int mode, void *psi, int
     if (g->scheme != SSGP_SCHEME_PAPER && mode != MODE_ADJ) {
         a.strang = g->scheme == SSGP_SCHEME_STRANG ? 1 : 0;
         a.ramp = T.ramp[mode].template as<cx<R>>();
-        for (int q = 0; q < 9; ++q) a.rot[q] = tor<R>(g->uso_rot[q]);
+        for (int q = 0; q < 9; ++q) a.rotr[q] = (R)g->uso_wr[q];
+        a.rotphased = 0;
+        for (int j = 0; j < 3; ++j) {
+            a.rotp[j] = g->uso_p[j];
+            if (g->uso_p[j] != 0) a.rotphased = 1;
+        }
         for (int c = 0; c < 3; ++c) {
             a.cu[c] = T.xu[mode][c].coef();
             a.rdiag_u[c] = T.xu[mode][c].rdiag;

@@ -618,18 +618,66 @@ template <typename R> struct XArgs {
     unsigned qxmask;           // bit 3j+j' set where qx[j][j'] != 0
     // Unitary-SO scheme (x-derivative SO forms; no qx terms then): the SO
     // term is solved together with CN_x.  In the eigenbasis of the SO spin
-    // matrix (columns of rot, row-major rot[3 j + c]) component c is a
-    // tridiagonal Toeplitz system with off-diagonals of equal modulus; the
-    // diagonal similarity by the unit phases ramp[c][i] makes it symmetric,
-    // and it is solved like CN_x with its own tables cu[c] and rdiag_u[c].
-    const cx<R> *ramp;         // [3][nx], or nullptr: the paper's scheme
-    cx<R> rot[9];
+    // matrix component c is a tridiagonal Toeplitz system with off-diagonals
+    // of equal modulus; the diagonal similarity by unit phases (the ramp of
+    // line c) makes it symmetric, and it is solved like CN_x with its own
+    // tables cu[c] and rdiag_u[c].  The basis change: uso_in / uso_out.
+    const cx<R> *ramp;         // [nx]: the ramp of line 0, or nullptr: the paper's scheme
+    R rotr[9];                 // Wr (row j: component, column c: eigenvector)
+    int rotp[3];               // the phase of row j: i^rotp[j]
+    int rotphased;             // some rotp[j] != 0
     LineCoef<R> cu[3];
     cx<R> rdiag_u[3];
     int strang;                // 1: the second-order pointwise stages (with ramp)
 };
 
 constexpr int XPASS_THREADS = 256;
+
+// ------------------------------------------- unitary-SO basis change ---
+// The eigenvector matrix of the SO spin matrix (row j: component, column c:
+// eigenvector) is W = diag(i^p_j) Wr with Wr real, and the eigenvalues are
+// (lambda, 0, -lambda), so the phase ramps of lines 1 and 2 are 1 and the
+// conjugate of line 0's (the host builds them so).  Into the symmetrised
+// basis: w_c = conj(ramp_c) sum_j Wr[j][c] i^-p_j v_j; back:
+// v_j = i^p_j sum_c Wr[j][c] ramp_c w_c.  Wr holds real numbers, so each
+// term is two multiply-adds.
+template <typename R> __device__ __forceinline__ cx<R> mul_ipow(cx<R> v, int k) {  // v i^k
+    switch (k & 3) {
+    case 1: return mk(-v.y, v.x);
+    case 2: return mk(-v.x, -v.y);
+    case 3: return mk(v.y, -v.x);
+    default: return v;
+    }
+}
+template <typename R> __device__ __forceinline__ cx<R> uso_ramp_line(int c, cx<R> ramp0) {
+    return c == 0 ? ramp0 : c == 1 ? mk(R(1), R(0)) : conj(ramp0);
+}
+template <typename R, typename A> __device__ __forceinline__ void uso_in(const A &a, cx<R> (&v)[3], cx<R> ramp0) {
+    if (a.rotphased)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v[j] = mul_ipow(v[j], 4 - a.rotp[j]);
+    cx<R> w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[c] = a.rotr[c] * v[0] + a.rotr[3 + c] * v[1] + a.rotr[6 + c] * v[2];
+    v[0] = conj(ramp0) * w[0];
+    v[1] = w[1];
+    v[2] = ramp0 * w[2];
+}
+template <typename R, typename A> __device__ __forceinline__ void uso_rotate_out(const A &a, cx<R> (&w)[3]) {
+    cx<R> v[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) v[j] = a.rotr[3 * j] * w[0] + a.rotr[3 * j + 1] * w[1] + a.rotr[3 * j + 2] * w[2];
+    if (a.rotphased)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v[j] = mul_ipow(v[j], a.rotp[j]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) w[j] = v[j];
+}
+template <typename R, typename A> __device__ __forceinline__ void uso_out(const A &a, cx<R> (&w)[3], cx<R> ramp0) {
+    w[0] = ramp0 * w[0];
+    w[2] = conj(ramp0) * w[2];
+    uso_rotate_out(a, w);
+}
 // 1D kernel: wavefronts 0-2 solve the three component lines; all of them
 // share the pointwise work (more wavefronts where the chunk registers allow)
 __host__ __device__ constexpr int step1d_threads(int L) { return L >= 16 ? 256 : 512; }
@@ -858,17 +906,15 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         }
     }
     if constexpr (USO) {
-        // into the symmetrised eigenbasis: conj(ramp) * (rot^H v)
+        // into the symmetrised eigenbasis
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             const int i = i0 + k;
             if (FULL || i < nx) {
-                cx<R> w[3];
+                cx<R> w[3] = {v[0][k], v[1][k], v[2][k]};
+                uso_in(a, w, a.ramp[i]);
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    w[c] = conj(a.rot[c]) * v[0][k] + conj(a.rot[3 + c]) * v[1][k] + conj(a.rot[6 + c]) * v[2][k];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) v[c][k] = conj(a.ramp[c * nx + i]) * w[c];
+                for (int c = 0; c < 3; ++c) v[c][k] = w[c];
             }
         }
     }
@@ -1026,16 +1072,15 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     if constexpr (USO) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) bwd_fix<R, KM>(r[j], len, coef(j), carry[j]);
-        // back from the symmetrised eigenbasis: rot (ramp * r)
+        // back from the symmetrised eigenbasis
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             const int i = i0 + k;
             if (FULL || i < nx) {
-                cx<R> w[3];
+                cx<R> w[3] = {r[0][k], r[1][k], r[2][k]};
+                uso_out(a, w, a.ramp[i]);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) w[c] = a.ramp[c * nx + i] * r[c][k];
-#pragma unroll
-                for (int j = 0; j < 3; ++j) r[j][k] = a.rot[3 * j] * w[0] + a.rot[3 * j + 1] * w[1] + a.rot[3 * j + 2] * w[2];
+                for (int j = 0; j < 3; ++j) r[j][k] = w[j];
             }
         }
     } else {
@@ -1436,8 +1481,10 @@ template <typename R> struct Args1D {
                                // time; real time when asked for)
     double *renorm_out;        // last step's {d, N, fallback}, or nullptr
     // unitary-SO scheme, as in XArgs (line j of the rotated state uses cu[j])
-    const cx<R> *ramp;         // [3][nx], or nullptr
-    cx<R> rot[9];
+    const cx<R> *ramp;         // [nx], or nullptr
+    R rotr[9];
+    int rotp[3];
+    int rotphased;
     LineCoef<R> cu[3];
     cx<R> rdiag_u[3];
     int strang;                // 1: Strang scheme (with ramp)
@@ -1491,12 +1538,8 @@ __global__ void __launch_bounds__(step1d_threads(L)) step1d_kernel(Args1D<R> a) 
                 pointwise(p, z, m, R(0.5) * xv * xv, a.m);
             }
             if constexpr (USO) {
-                const cx<R> v[3] = {p, z, m};
-                cx<R> w[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    w[c] = conj(a.ramp[c * nx + i]) *
-                           (conj(a.rot[c]) * v[0] + conj(a.rot[3 + c]) * v[1] + conj(a.rot[6 + c]) * v[2]);
+                cx<R> w[3] = {p, z, m};
+                uso_in(a, w, a.ramp[i]);
                 p = w[0];
                 z = w[1];
                 m = w[2];
@@ -1519,15 +1562,14 @@ __global__ void __launch_bounds__(step1d_threads(L)) step1d_kernel(Args1D<R> a) 
             if (solver) {
 #pragma unroll
                 for (int t = 0; t < L; ++t)
-                    if (t < len) wj[sidx<L>(start + t)] = a.ramp[jj * nx + start + t] * r[t];
+                    if (t < len) wj[sidx<L>(start + t)] = uso_ramp_line(jj, a.ramp[start + t]) * r[t];
             }
             __syncthreads();
             for (int i = tid; i < nx; i += NT) {
                 const int si = sidx<L>(i);
-                const cx<R> w0 = s[si], w1 = s[ld + si], w2 = s[2 * ld + si];
-                cx<R> p = a.rot[0] * w0 + a.rot[1] * w1 + a.rot[2] * w2;
-                cx<R> z = a.rot[3] * w0 + a.rot[4] * w1 + a.rot[5] * w2;
-                cx<R> m = a.rot[6] * w0 + a.rot[7] * w1 + a.rot[8] * w2;
+                cx<R> w[3] = {s[si], s[ld + si], s[2 * ld + si]};
+                uso_rotate_out(a, w);
+                cx<R> p = w[0], z = w[1], m = w[2];
                 if constexpr (P2) {
                     const R xv = a.x0 + R(i) * a.dx;
                     Model<R> Mt = a.m;
