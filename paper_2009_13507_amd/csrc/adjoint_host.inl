@@ -6,7 +6,8 @@ static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps)
         return fail(SSGP_EINVAL, "the adjoint supports SO forms with x derivatives only");
     SSGP_TRY(build_tables<R>(g, MODE_ADJ));
     const int rows = g->dim == 2 ? g->ny : 1;
-    SSGP_TRY(g->adj_partials.ensure(sizeof(double) * rows));
+    // per-row dL/dOmega partials of every step of the call, then the step sums
+    SSGP_TRY(g->adj_partials.ensure(sizeof(double) * ((size_t)rows * nsteps + nsteps)));
     const size_t se = (size_t)3 * plane_of(*g);
     const long long n0 = g->step_index - nsteps;
     Tables<R> &T = tables<R>(g);
@@ -15,11 +16,6 @@ static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps)
     for (int k = nsteps - 1; k >= 0; --k) {
         const long long n = n0 + k;
         const double omega = omega_at(*g, n);
-        int seg = 0;
-        if (!g->omega_sched.empty()) {
-            long long s = n / g->steps_per_seg;
-            seg = (int)std::max<long long>(0, std::min<long long>(s, (long long)g->omega_sched.size() - 1));
-        }
         if (g->dim == 2) {
             YArgs<R> ya = y_args<R>(g, MODE_ADJ, lam, nullptr);
             SSGP_TRY(launch_y<R>(*g, ya, ys));
@@ -41,11 +37,12 @@ static int adjoint_steps(ssgp_grid g, const void *states, void *lam, int nsteps)
         fill_so<R>(tmp, *g, MODE_ADJ);
         for (int q = 0; q < 9; ++q) a.qx[q] = tmp.qx[q];
         a.qxmask = tmp.qxmask;
-        a.omega_partials = g->adj_partials.as<double>();
+        a.omega_partials = g->adj_partials.as<double>() + (size_t)k * rows;
         LAUNCH_TRY(launch_adj_xpass<R>(lc(*g), a, Lx, rows));
-        LAUNCH_TRY(launch_omega_accumulate(lc(*g), g->adj_partials.as<double>(), rows, g->omega_acc.as<double>(),
-                                           seg));
     }
+    double *partials = g->adj_partials.as<double>();
+    LAUNCH_TRY(launch_omega_accumulate(lc(*g), partials, rows, nsteps, partials + (size_t)rows * nsteps, n0,
+                                       g->steps_per_seg, (int)g->omega_sched.size(), g->omega_acc.as<double>()));
     g->step_index = n0;
     return SSGP_OK;
 }

@@ -44,20 +44,38 @@ __global__ void __launch_bounds__(256) obs_finalize_kernel(const double *partial
     }
 }
 
-// Adds the per-row Omega derivatives of one adjoint step (fixed order) to
-// acc[seg].
-__global__ void __launch_bounds__(256) omega_accumulate_kernel(const double *partials, int nrows, double *acc,
-                                                               int seg) {
+// dL/dOmega over a call's adjoint steps.  The per-row partials of the k-th
+// step of the call are partials[k * nrows + row].  omega_step_sums_kernel
+// sums each step's rows in a fixed tree (one workgroup per step);
+// omega_accumulate_kernel then adds the step sums to their Omega segments in
+// the order the steps are taken back (k = nsteps - 1 down to 0; step index
+// n0 + k, segment (n0 + k) / steps_per_seg clamped to [0, nseg), or 0
+// without a schedule, nseg = 0).
+__global__ void __launch_bounds__(256) omega_step_sums_kernel(const double *partials, int nrows, double *sums) {
     __shared__ double red[256];
+    const double *p = partials + (long long)blockIdx.x * nrows;
     double s = 0.0;
-    for (int q = threadIdx.x; q < nrows; q += 256) s += partials[q];
+    for (int q = threadIdx.x; q < nrows; q += 256) s += p[q];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) acc[seg] += red[0];
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__global__ void omega_accumulate_kernel(const double *sums, int nsteps, long long n0, int steps_per_seg, int nseg,
+                                        double *acc) {
+    if (threadIdx.x != 0) return;
+    for (int k = nsteps - 1; k >= 0; --k) {
+        long long seg = 0;
+        if (nseg > 0) {
+            seg = (n0 + k) / steps_per_seg;
+            seg = seg < 0 ? 0 : seg >= nseg ? nseg - 1 : seg;
+        }
+        acc[seg] += sums[k];
+    }
 }
 
 // Clears the batched step's barrier words before a launch; a barrier

@@ -45,7 +45,8 @@ template <typename R> hipError_t launch_scale(const Launch &c, cx<R> *psi, long 
 template <typename R> hipError_t launch_obs(const Launch &c, const ObsArgs<R> &a, int blocks);
 hipError_t launch_renorm_finalize(const Launch &c, const double *partials, int ntiles, RenormSpec sp, double *out);
 hipError_t launch_obs_finalize(const Launch &c, const double *partials, int nblocks, double *out);
-hipError_t launch_omega_accumulate(const Launch &c, const double *partials, int nrows, double *acc, int seg);
+hipError_t launch_omega_accumulate(const Launch &c, const double *partials, int nrows, int nsteps, double *sums,
+                                   long long n0, int steps_per_seg, int nseg, double *acc);
 
 // batched imaginary-time step
 enum { BATCH_PHASE_X = 0, BATCH_PHASE_Y = 1, BATCH_PHASE_R = 2, BATCH_PHASE_SCALE = 3 };

@@ -14,8 +14,11 @@ hipError_t launch_obs_finalize(const Launch &c, const double *partials, int nblo
     return hipGetLastError();
 }
 
-hipError_t launch_omega_accumulate(const Launch &c, const double *partials, int nrows, double *acc, int seg) {
-    omega_accumulate_kernel<<<1, 256, 0, c.stream>>>(partials, nrows, acc, seg);
+hipError_t launch_omega_accumulate(const Launch &c, const double *partials, int nrows, int nsteps, double *sums,
+                                   long long n0, int steps_per_seg, int nseg, double *acc) {
+    if (nsteps < 1) return hipSuccess;
+    omega_step_sums_kernel<<<nsteps, 256, 0, c.stream>>>(partials, nrows, sums);
+    omega_accumulate_kernel<<<1, 64, 0, c.stream>>>(sums, nsteps, n0, steps_per_seg, nseg, acc);
     return hipGetLastError();
 }
 
