@@ -941,48 +941,57 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     exchange_edges(v, 0);
     __syncthreads();
     cx<R> u[3][KM];
-    {
-        cx<R> vb[3], va[3];
+    cx<R> vb[3], va[3];
 #pragma unroll
-        for (int jp = 0; jp < 3; ++jp) outer(v, 0, jp, vb[jp], va[jp]);
+    for (int jp = 0; jp < 3; ++jp) outer(v, 0, jp, vb[jp], va[jp]);
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int k = 0; k < KM; ++k) u[j][k] = v[j][k];
-        // one coefficient at a time over the thread's points (the terms of
-        // each point are still added in the order jp = 0, 1, 2)
+        for (int k = 0; k < KM; ++k) u[j][k] = v[j][k];
+    // one coefficient at a time over the thread's points (the terms of each
+    // point are still added in the order jp = 0, 1, 2)
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int jp = 0; jp < 3; ++jp)
-                if (a.qxmask & (1u << (3 * j + jp))) {
-                    const cx<R> q = a.qx[3 * j + jp];
+        for (int jp = 0; jp < 3; ++jp)
+            if (a.qxmask & (1u << (3 * j + jp))) {
+                const cx<R> q = a.qx[3 * j + jp];
 #pragma unroll
-                    for (int k = 0; k < KM; ++k) {
-                        const cx<R> pv = k > 0 ? v[jp][k > 0 ? k - 1 : 0] : vb[jp];
-                        const cx<R> nv = k + 1 < KM ? v[jp][k + 1 < KM ? k + 1 : 0] : va[jp];
-                        u[j][k] = cfma(q, nv - pv, u[j][k]);
-                    }
+                for (int k = 0; k < KM; ++k) {
+                    const cx<R> pv = k > 0 ? v[jp][k > 0 ? k - 1 : 0] : vb[jp];
+                    const cx<R> nv = k + 1 < KM ? v[jp][k + 1 < KM ? k + 1 : 0] : va[jp];
+                    u[j][k] = cfma(q, nv - pv, u[j][k]);
                 }
+            }
 #pragma unroll
-        for (int k = 0; k < KM; ++k)
-            if (!FULL && i0 + k >= nx)
+    for (int k = 0; k < KM; ++k)
+        if (!FULL && i0 + k >= nx)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) u[j][k] = czero<R>();
-    }
+            for (int j = 0; j < 3; ++j) u[j][k] = czero<R>();
 
-    // ---- right-hand side (I - sT) u / o
-    exchange_edges(u, 1);
-    __syncthreads();
+    // ---- right-hand side (I - sT) u / o; without SO terms (the y-derivative
+    // forms after their pointwise + SO pass, no coupling) u is v, whose outer
+    // values are at hand: no second exchange
+    cx<R> ub[3], ua[3];  // u just before and just after this thread's points
+    if (!USO && a.qxmask == 0) {  // (the unitary-SO pass keeps the exchange: it measured faster so)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            ub[jj] = vb[jj];
+            ua[jj] = va[jj];
+        }
+    } else {
+        exchange_edges(u, 1);
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) outer(u, 1, jj, ub[jj], ua[jj]);
+    }
     cx<R> r[3][KM];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        cx<R> ub, ua;
-        outer(u, 1, j, ub, ua);
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
-            const cx<R> pu = k > 0 ? u[j][k > 0 ? k - 1 : 0] : ub;
-            const cx<R> nu = k + 1 < KM ? u[j][k + 1 < KM ? k + 1 : 0] : ua;
+            const cx<R> pu = k > 0 ? u[j][k > 0 ? k - 1 : 0] : ub[j];
+            const cx<R> nu = k + 1 < KM ? u[j][k + 1 < KM ? k + 1 : 0] : ua[j];
             r[j][k] = (FULL || i0 + k < nx) ? cn_rhs(USO ? a.rdiag_u[j] : a.rdiag, u[j][k], pu + nu) : czero<R>();
         }
     }

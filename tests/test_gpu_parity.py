@@ -93,6 +93,21 @@ def test_2d_y_derivative_so_forms(so, imag):
     assert close(got, ref), (rel(got, ref), maxrel(got, ref))
 
 
+@pytest.mark.parametrize("nx,ny", [(64, 16), (128, 48), (65, 17), (63, 15), (127, 33), (1, 40), (40, 1),
+                                   (200, 7)])
+@pytest.mark.parametrize("imag", [False, True])
+def test_y_derivative_so_tile_edges(nx, ny, imag):
+    """Rashba on grids that fill the pointwise + SO pass's 64 x 16 tiles
+    exactly, leave ragged tails in x, in y or in both, or hold a single row or
+    column (halo columns and rows at the grid's ghosts)."""
+    dx = 0.25
+    p = dict(c0=3.0, c2=-0.4, gamma=0.7, omega=0.2, dt=2e-3, so=api.SO_RASHBA)
+    psi0 = start_state(2, nx, ny, dx, dx, seed=nx + 7 * ny) + W.random_state((3, ny, nx), nx * ny, 1e-3)
+    got, _ = gpu_run(psi0, dx, dx, imag, 4, **p)
+    ref = oracle.step(ocfg(2, nx, ny, dx, dx, imag, **p), psi0, 4)
+    assert close(got, ref), (rel(got, ref), maxrel(got, ref))
+
+
 @pytest.mark.parametrize("dim", [1, 2])
 def test_fixed_magnetisation_renorm(dim):
     nx, ny, dx = (200, 1, 0.1) if dim == 1 else (64, 48, 0.3)
