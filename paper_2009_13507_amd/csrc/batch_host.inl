@@ -128,6 +128,20 @@ template <typename R> static int batch_build(ssgp_batch b, const long long *offs
         for (int q : xi)
             if (host[q >> 10].Lx == 8) ++b->nrows2;
     b->nyitems = (int)yi.size();
+    {
+        // y items in blocks of 128 list entries: the per-phase launch runs
+        // workgroup q on XCD q mod 8, so XCD k gets entries 16k .. 16k + 15
+        // of the block, 16 adjacent column tiles of one instance and
+        // component (measured: 0.314 -> 0.303 ms per complex128 step; 4 per
+        // XCD gave nothing, 8 nearly as much)
+        constexpr int G = 16, BLK = 8 * G;
+        std::vector<int> p(yi);
+        const int full = (int)yi.size() / BLK * BLK;
+        for (int base = 0; base < full; base += BLK)
+            for (int k = 0; k < 8; ++k)
+                for (int m = 0; m < G; ++m) p[(size_t)(base + k + 8 * m)] = yi[(size_t)(base + G * k + m)];
+        yi.swap(p);
+    }
     SSGP_TRY(b->xitems.ensure(sizeof(int) * xi.size()));
     SSGP_TRY(b->yitems.ensure(sizeof(int) * yi.size()));
     HIP_TRY(hipMemcpyAsync(b->xitems.p, xi.data(), sizeof(int) * xi.size(), hipMemcpyHostToDevice, b->stream));
