@@ -583,6 +583,10 @@ static XArgs<R> x_args(ssgp_grid g, int mode, const void *src, void *dst, double
     a.m = model<R>(*g, mode, omega);
     a.dscale = dscale;
     a.pointwise = 1;
+    // adjacent rows on one XCD, 16 at a time: at 512 rows the x-pass is 5%
+    // faster (and the y-pass after it too); measured no gain at 1024 rows and
+    // a loss at 256, where it stays off
+    a.rowgrp = (a.ny >= 512 && a.ny < 1024) ? 16 : 0;
     a.cx_ = T.xb[mode].coef();
     a.rdiag = T.x[mode].rdiag;
     fill_so<R>(a, *g, mode);

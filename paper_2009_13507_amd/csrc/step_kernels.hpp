@@ -629,6 +629,9 @@ template <typename R> struct XArgs {
     LineCoef<R> cu[3];
     cx<R> rdiag_u[3];
     int strang;                // 1: the second-order pointwise stages (with ramp)
+    int rowgrp;                // > 0: workgroup b takes row (b / (8 g)) 8 g + (b mod 8) g + (b mod 8g) / 8
+                               // (g = rowgrp): the 8 XCDs, which take workgroups round-robin, each
+                               // get g adjacent rows of every block of 8 g; 0: row b
 };
 
 constexpr int XPASS_THREADS = 256;
@@ -1111,7 +1114,11 @@ __attribute__((amdgpu_waves_per_eu(P2 ? (KM <= 4 ? 2 : 1)
 xpass_kernel(XArgs<R> a) {
     __shared__ XShared<R, KM> sh;
     const int nx = FULL ? XPASS_THREADS * KM : a.nx;
-    const int row = blockIdx.x;
+    int row = blockIdx.x;
+    if (a.rowgrp > 0) {
+        const int g = a.rowgrp, blk = 8 * g;
+        if (row < (int)gridDim.x / blk * blk) row = row / blk * blk + (row % blk % 8) * g + row % blk / 8;
+    }
     const int i0 = threadIdx.x * KM;
     const cx<R> *src = a.src + (long long)row * nx;
     cx<R> v[3][KM];
