@@ -349,6 +349,7 @@ template <typename R> struct Tables {
     CNDev<R> y[NMODES];
     CNDev<R> xu[NMODES][3];  // unitary-SO scheme: the three symmetrised lines (as x in
     DevBuf ramp[NMODES];     //   1D, as xb in 2D) and the phase ramp of line 0 [nx]
+    DevBuf uso_lines[NMODES];  // UsoLines<R> of xu (2D x-pass)
 };
 
 struct ssgp_grid_s : GridCore {
@@ -463,10 +464,15 @@ template <typename R> static int build_uso(ssgp_grid g, int mode, int L, int nch
     }
     const double th = std::arg(rho0);
     for (int i = 0; i < g->nx; ++i) ramp[(size_t)i] = tor<R>(cd(std::cos(th * i), std::sin(th * i)));
+    UsoLines<R> ul{};
     for (int c = 0; c < 3; ++c) {
         tab[c].levels = levels;
         SSGP_TRY(upload_cn<R>(T.xu[mode][c], tab[c], g->nx, L, nchunks, g->stream));
+        ul.cu[c] = T.xu[mode][c].coef();
+        ul.rdiag_u[c] = T.xu[mode][c].rdiag;
     }
+    SSGP_TRY(T.uso_lines[mode].ensure(sizeof(UsoLines<R>)));
+    HIP_TRY(hipMemcpyAsync(T.uso_lines[mode].p, &ul, sizeof(ul), hipMemcpyHostToDevice, g->stream));
     SSGP_TRY(T.ramp[mode].ensure(ramp.size() * sizeof(cx<R>)));
     HIP_TRY(hipMemcpyAsync(T.ramp[mode].p, ramp.data(), ramp.size() * sizeof(cx<R>), hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
@@ -600,9 +606,12 @@ static XArgs<R> x_args(ssgp_grid g, int mode, const void *src, void *dst, double
             a.rotp[j] = g->uso_p[j];
             if (g->uso_p[j] != 0) a.rotphased = 1;
         }
+        a.ul = T.uso_lines[mode].template as<UsoLines<R>>();
+        a.uso_head = 1;
         for (int c = 0; c < 3; ++c) {
             a.cu[c] = T.xu[mode][c].coef();
             a.rdiag_u[c] = T.xu[mode][c].rdiag;
+            a.uso_head = std::max(a.uso_head, a.cu[c].head);
         }
         a.qxmask = 0;  // the SO term is in the line solve
     }

@@ -599,6 +599,14 @@ __device__ __forceinline__ void wave_tile_sums(const double *partials, int ntile
         for (int j = 0; j < 3; ++j) s[j] += __shfl_down(s[j], d, 64);
 }
 
+// The three symmetrised lines of the unitary-SO scheme in device memory, for
+// the x-pass variant whose scalar registers run short with them as kernel
+// arguments (held for the whole pass, they spill).
+template <typename R> struct UsoLines {
+    LineCoef<R> cu[3];
+    cx<R> rdiag_u[3];
+};
+
 template <typename R> struct XArgs {
     const cx<R> *src;          // state read (3 planes)
     cx<R> *dst;                // state written (may equal src)
@@ -628,6 +636,9 @@ template <typename R> struct XArgs {
     int rotphased;             // some rotp[j] != 0
     LineCoef<R> cu[3];
     cx<R> rdiag_u[3];
+    const UsoLines<R> *ul;     // cu and rdiag_u again, in device memory (the Strang pass reads
+                               // them there: its scalar registers run short)
+    int uso_head;              // the longest of the three pivot heads (host: coefficient mode)
     int strang;                // 1: the second-order pointwise stages (with ramp)
     int rowgrp;                // > 0: workgroup b takes row (b / (8 g)) 8 g + (b mod 8) g + (b mod 8g) / 8
                                // (g = rowgrp): the 8 XCDs, which take workgroups round-robin, each
@@ -995,24 +1006,27 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         for (int k = 0; k < KM; ++k) {
             const cx<R> pu = k > 0 ? u[j][k > 0 ? k - 1 : 0] : ub[j];
             const cx<R> nu = k + 1 < KM ? u[j][k + 1 < KM ? k + 1 : 0] : ua[j];
-            r[j][k] = (FULL || i0 + k < nx) ? cn_rhs(USO ? a.rdiag_u[j] : a.rdiag, u[j][k], pu + nu) : czero<R>();
+            r[j][k] = (FULL || i0 + k < nx) ? cn_rhs(USO ? (P2 ? a.ul->rdiag_u[j] : a.rdiag_u[j]) : a.rdiag, u[j][k], pu + nu)
+                                            : czero<R>();
         }
     }
 
     // ---- Crank-Nicolson solve of the three lines, chunk = this thread's points
     const int len = FULL ? KM : max(0, min(KM, nx - i0));
     // one coefficient set for the three lines, or (USO) one per line
-    const ChunkCoef<R, KM, CM> cpl(USO ? a.cu[0] : a.cx_, i0);
-    const ChunkCoef<R, KM, CM> cpl1(USO ? a.cu[1] : a.cx_, i0);
-    const ChunkCoef<R, KM, CM> cpl2(USO ? a.cu[2] : a.cx_, i0);
+    // the unitary-SO lines' coefficients (the Strang pass reads them from memory)
+    const LineCoef<R> *ucf = P2 ? a.ul->cu : a.cu;
+    const ChunkCoef<R, KM, CM> cpl(USO ? ucf[0] : a.cx_, i0);
+    const ChunkCoef<R, KM, CM> cpl1(USO ? ucf[1] : a.cx_, i0);
+    const ChunkCoef<R, KM, CM> cpl2(USO ? ucf[2] : a.cx_, i0);
     auto coef = [&](int j) -> const ChunkCoef<R, KM, CM> & { return j == 0 ? cpl : j == 1 ? cpl1 : cpl2; };
     const cx<R> Ak = a.cx_.chunkA[tid];
-    const int levels = USO ? a.cu[0].levels : a.cx_.levels;  // (USO: the host gives the three the same)
+    const int levels = USO ? ucf[0].levels : a.cx_.levels;  // (USO: the host gives the three the same)
     cx<R> A[3], B[3];
     // forward sweep: chunk eliminations, scan, carries across wavefronts
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        A[j] = USO ? a.cu[j].chunkA[tid] : Ak;
+        A[j] = USO ? ucf[j].chunkA[tid] : Ak;
         B[j] = fwd_local<R, KM>(r[j], len, USO ? coef(j) : cpl);
     }
     wave_scan_up3<R>(A, B, levels);
@@ -1051,7 +1065,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     // back substitution: chunk sweeps, reverse scan, carries
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        A[j] = USO ? a.cu[j].chunkA[tid] : Ak;
+        A[j] = USO ? ucf[j].chunkA[tid] : Ak;
         B[j] = bwd_local<R, KM>(r[j], len, USO ? coef(j) : cpl);
     }
     wave_scan_down3<R>(A, B, levels);
