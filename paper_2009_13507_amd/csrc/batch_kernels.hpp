@@ -20,8 +20,9 @@
 // item functions with the same arithmetic, so their results are identical.
 //
 // Barrier: arrivals are counted on a global word and waiters are released by
-// a generation word (vector atomics at agent scope, with fences on both
-// sides so that the state written before the barrier is visible after it on
+// a generation word (vector atomics at agent scope; one agent-scope release
+// fence per workgroup before its arrival and one acquire fence after the
+// wait, so that the state written before the barrier is visible after it on
 // every XCD).  Every wait is bounded: a workgroup whose wait exceeds the
 // spin budget raises a stop word and leaves; every other workgroup sees the
 // word at its next barrier and leaves too, so the grid always drains.
@@ -73,20 +74,26 @@ __device__ __forceinline__ double coherent_load(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Device-wide barrier; returns false when the grid must stop.
+// Device-wide barrier; returns false when the grid must stop.  Every
+// thread's stores are complete (workgroup-scope release) before the
+// workgroup barrier; thread 0 then makes them visible to the other XCDs
+// (agent-scope release fence) and arrives, waits on the generation word with
+// relaxed loads (no cache invalidation per poll) and takes one agent-scope
+// acquire fence when it changes, which the workgroup barrier passes on.
 __device__ __forceinline__ bool grid_sync(unsigned *bar, long long spin_limit) {
     __shared__ int stop;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == gridDim.x - 1) {
             __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             long long spins = 0;
-            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
                 if (++spins > spin_limit) {
                     __hip_atomic_store(bar + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -95,10 +102,10 @@ __device__ __forceinline__ bool grid_sync(unsigned *bar, long long spin_limit) {
                 __builtin_amdgcn_s_sleep(2);
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         stop = __hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
     }
     __syncthreads();
-    __threadfence();
     return !stop;
 }
 
