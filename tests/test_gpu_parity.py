@@ -53,6 +53,7 @@ def start_state(dim, nx, ny, dx, dy, seed=0):
 
 
 SHAPES_2D = [(96, 80), (37, 29), (130, 67), (64, 64), (1, 7), (5, 1), (200, 3), (513, 33),
+             (40, 512), (33, 700), (17, 1023),  # rows 512-1023: the XCD row grouping, full blocks and tails
              (256, 20), (512, 9), (1024, 5), (2048, 3), (1500, 4), (3, 2048), (5, 1500),
              (1, 1), (2, 2)]
 
