@@ -7,18 +7,40 @@
 //
 // Launch shapes: k > 0 is the persistent kernel with k workgroups per
 // compute unit (every workgroup resident, device-wide barriers between the
-// phases); -1 is one kernel launch per phase.  All shapes run the same item
-// functions, so the results do not depend on the shape.  The autotuner
-// times every shape on a scratch copy of the pool at the first step call and
-// keeps the fastest.  A run of n steps is replayed as graphs of 2^i steps
-// (binary decomposition of n); a graph ends with the RENORM scale of its last
-// step, which gives bitwise the same state as one longer run, since the next
-// step would apply the same rounded product first.
+// phases); -1 is one kernel launch per phase; -2 and -4 split the instances
+// into 2 or 4 groups of about equal points, each group stepped by its own
+// phase launches on a stream of its own (forked from the batch's stream and
+// joined back), so that the groups drift out of phase and one group's x rows
+// run beside another's y tiles.  All shapes run the same item functions, so
+// the results do not depend on the shape.  The autotuner times every shape
+// on a scratch copy of the pool at the first step call and keeps the
+// fastest.  A run of n steps is replayed as graphs of 2^i steps (binary
+// decomposition of n); a graph ends with the RENORM scale of its last step,
+// which gives bitwise the same state as one longer run, since the next step
+// would apply the same rounded product first.
 
 static constexpr long long BATCH_SPIN_LIMIT = 1LL << 21;  // a second or more per barrier wait
 static constexpr int BATCH_LOG2_PERSISTENT = 12;          // persistent graphs of up to 4096 steps
 static constexpr int BATCH_LOG2_PHASED = 6;               // phase-launch graphs of up to 64 steps
 static constexpr int BATCH_MAX_INSTANCES = 1 << 16;
+// shapes -2 and -4 (8 groups measured slower than 4, 0.288 against 0.275 ms
+// per complex128 C4 step: a process has 4 hardware queues by default, so
+// 8 streams share them)
+static constexpr int BATCH_GROUP_LEVELS = 2;
+static constexpr int BATCH_MAX_GROUPS = 1 << BATCH_GROUP_LEVELS;
+
+// k for the grouped shape -2^k (1 <= k <= BATCH_GROUP_LEVELS), else 0.
+static int batch_group_level(int shape) {
+    for (int k = 1; k <= BATCH_GROUP_LEVELS; ++k)
+        if (shape == -(1 << k)) return k;
+    return 0;
+}
+
+// One group's item lists: x rows [xoff, xoff + nrows) (the first nrows2 by
+// two wavefronts), y tiles [yoff, yoff + nyitems), instances [roff, roff + ninst).
+struct BatchGroup {
+    int xoff, nrows, nrows2, yoff, nyitems, roff, ninst;
+};
 
 template <typename R> struct BatchTabs {
     DevBuf inst;                // BatchInst<R>[n]
@@ -30,6 +52,10 @@ struct ssgp_batch_s {
     void *pool = nullptr;
     size_t pool_bytes = 0;      // extent of the pool the instances use
     hipStream_t stream = nullptr, cap = nullptr;
+    hipStream_t side[BATCH_MAX_GROUPS - 1] = {};  // the streams of groups 1, 2, ...
+    hipEvent_t evf = nullptr, evj[BATCH_MAX_GROUPS - 1] = {};
+    std::vector<BatchGroup> grouped[BATCH_GROUP_LEVELS];  // [k - 1]: the instances in 2^k groups (none if fewer instances)
+    DevBuf gitems;                       // the groups' item lists, concatenated
     std::vector<ssgp_grid> grids;
     int nrows = 0, nrows2 = 0, nyitems = 0, ntiles = 0;
     DevBuf xitems, yitems, partials, renorm, bar;
@@ -51,6 +77,11 @@ struct ssgp_batch_s {
         drop_graphs();
         for (ssgp_grid g : grids) ssgp_destroy(g);
         if (cap) (void)hipStreamDestroy(cap);
+        for (int g = 0; g < BATCH_MAX_GROUPS - 1; ++g) {
+            if (side[g]) (void)hipStreamDestroy(side[g]);
+            if (evj[g]) (void)hipEventDestroy(evj[g]);
+        }
+        if (evf) (void)hipEventDestroy(evf);
     }
 };
 
@@ -62,6 +93,40 @@ template <> BatchTabs<float> &btabs<float>(ssgp_batch b) { return b->t32; }
 template <typename R> static int batch_y_chunk(int ny) {
     const int P = BATCH_THREADS / BatchTX<R>::v;
     return pow2_at_least((ny + P - 1) / P);
+}
+
+// Item lists of a set of instances (ids in instance order).  x rows and y
+// tiles go the costliest first (rows by nx, tiles by ny), so that the
+// round-robin assignment over the workgroups ends evenly; the rows by two
+// wavefronts (x chunks of 8 points) come first.  y tiles go in blocks of 128
+// list entries: the per-phase launch runs workgroup q on XCD q mod 8, so XCD
+// k gets entries 16k .. 16k + 15 of the block, 16 adjacent column tiles of
+// one instance and component (measured: 0.314 -> 0.303 ms per complex128
+// step; 4 per XCD gave nothing, 8 nearly as much).  ri: the instances.
+template <typename R>
+static void batch_lists(const std::vector<BatchInst<R>> &host, std::vector<int> ids, std::vector<int> &xi, int &nrows2,
+                        std::vector<int> &yi, std::vector<int> &ri) {
+    ri = ids;
+    std::stable_sort(ids.begin(), ids.end(), [&](int u, int v) { return host[u].nx > host[v].nx; });
+    xi.clear();
+    for (int i : ids)
+        for (int r = 0; r < host[i].ny; ++r) xi.push_back((i << 10) | r);
+    nrows2 = 0;
+    if (batch_pair_rows<R>())
+        for (int q : xi)
+            if (host[q >> 10].Lx == 8) ++nrows2;
+    std::stable_sort(ids.begin(), ids.end(), [&](int u, int v) { return host[u].ny > host[v].ny; });
+    yi.clear();
+    for (int i : ids)
+        for (int j = 0; j < 3; ++j)
+            for (int t = 0; t < host[i].ntiles; ++t) yi.push_back((i << 8) | (j << 6) | t);
+    constexpr int G = 16, BLK = 8 * G;
+    std::vector<int> p(yi);
+    const int full = (int)yi.size() / BLK * BLK;
+    for (int base = 0; base < full; base += BLK)
+        for (int k = 0; k < 8; ++k)
+            for (int m = 0; m < G; ++m) p[(size_t)(base + k + 8 * m)] = yi[(size_t)(base + G * k + m)];
+    yi.swap(p);
 }
 
 template <typename R> static int batch_build(ssgp_batch b, const long long *offsets) {
@@ -108,44 +173,62 @@ template <typename R> static int batch_build(ssgp_batch b, const long long *offs
     SSGP_TRY(T.inst.ensure(sizeof(BatchInst<R>) * b->n));
     HIP_TRY(hipMemcpyAsync(T.inst.p, host.data(), sizeof(BatchInst<R>) * b->n, hipMemcpyHostToDevice, b->stream));
 
-    // work items, the costliest first (rows by nx, tiles by ny), so that the
-    // round-robin assignment over the workgroups ends evenly
-    std::vector<int> order(b->n);
-    for (int i = 0; i < b->n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return host[u].nx > host[v].nx; });
-    std::vector<int> xi;
-    for (int i : order)
-        for (int r = 0; r < host[i].ny; ++r) xi.push_back((i << 10) | r);
-    std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return host[u].ny > host[v].ny; });
-    std::vector<int> yi;
-    for (int i : order)
-        for (int j = 0; j < 3; ++j)
-            for (int t = 0; t < host[i].ntiles; ++t) yi.push_back((i << 8) | (j << 6) | t);
+    std::vector<int> all(b->n);
+    for (int i = 0; i < b->n; ++i) all[i] = i;
+    std::vector<int> xi, yi, ri;
+    int nrows2 = 0;
+    batch_lists<R>(host, all, xi, nrows2, yi, ri);
     b->nrows = (int)xi.size();
-    // rows by two wavefronts (x chunk of 8 points) come first in the list
-    b->nrows2 = 0;
-    if (batch_pair_rows<R>())
-        for (int q : xi)
-            if (host[q >> 10].Lx == 8) ++b->nrows2;
+    b->nrows2 = nrows2;
     b->nyitems = (int)yi.size();
-    {
-        // y items in blocks of 128 list entries: the per-phase launch runs
-        // workgroup q on XCD q mod 8, so XCD k gets entries 16k .. 16k + 15
-        // of the block, 16 adjacent column tiles of one instance and
-        // component (measured: 0.314 -> 0.303 ms per complex128 step; 4 per
-        // XCD gave nothing, 8 nearly as much)
-        constexpr int G = 16, BLK = 8 * G;
-        std::vector<int> p(yi);
-        const int full = (int)yi.size() / BLK * BLK;
-        for (int base = 0; base < full; base += BLK)
-            for (int k = 0; k < 8; ++k)
-                for (int m = 0; m < G; ++m) p[(size_t)(base + k + 8 * m)] = yi[(size_t)(base + G * k + m)];
-        yi.swap(p);
-    }
     SSGP_TRY(b->xitems.ensure(sizeof(int) * xi.size()));
     SSGP_TRY(b->yitems.ensure(sizeof(int) * yi.size()));
     HIP_TRY(hipMemcpyAsync(b->xitems.p, xi.data(), sizeof(int) * xi.size(), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->yitems.p, yi.data(), sizeof(int) * yi.size(), hipMemcpyHostToDevice, b->stream));
+
+    // the instances in 2 and 4 groups: by points, largest first, each to the
+    // group with the fewest points so far (the first such group on ties)
+    std::vector<int> gl;
+    for (int k = 1; k <= BATCH_GROUP_LEVELS; ++k) {
+        const int G = 1 << k;
+        b->grouped[k - 1].clear();
+        if (G > b->n) continue;
+        std::vector<int> bysize(all);
+        std::stable_sort(bysize.begin(), bysize.end(), [&](int u, int v) {
+            return (long long)host[u].nx * host[u].ny > (long long)host[v].nx * host[v].ny;
+        });
+        std::vector<std::vector<int>> members(G);
+        std::vector<long long> load(G, 0);
+        for (int i : bysize) {
+            int g = 0;
+            for (int h = 1; h < G; ++h)
+                if (load[h] < load[g]) g = h;
+            members[g].push_back(i);
+            load[g] += (long long)host[i].nx * host[i].ny;
+        }
+        for (int g = 0; g < G; ++g) {
+            std::sort(members[g].begin(), members[g].end());
+            std::vector<int> gx, gy, gr;
+            int g2 = 0;
+            batch_lists<R>(host, members[g], gx, g2, gy, gr);
+            BatchGroup bg{};
+            bg.xoff = (int)gl.size();
+            bg.nrows = (int)gx.size();
+            bg.nrows2 = g2;
+            gl.insert(gl.end(), gx.begin(), gx.end());
+            bg.yoff = (int)gl.size();
+            bg.nyitems = (int)gy.size();
+            gl.insert(gl.end(), gy.begin(), gy.end());
+            bg.roff = (int)gl.size();
+            bg.ninst = (int)gr.size();
+            gl.insert(gl.end(), gr.begin(), gr.end());
+            b->grouped[k - 1].push_back(bg);
+        }
+    }
+    if (!gl.empty()) {
+        SSGP_TRY(b->gitems.ensure(sizeof(int) * gl.size()));
+        HIP_TRY(hipMemcpyAsync(b->gitems.p, gl.data(), sizeof(int) * gl.size(), hipMemcpyHostToDevice, b->stream));
+    }
     SSGP_TRY(b->partials.ensure(sizeof(double) * 3 * b->ntiles));
     SSGP_TRY(b->renorm.ensure(sizeof(double) * 8 * b->n));
     SSGP_TRY(b->bar.ensure(sizeof(unsigned) * 4));
@@ -175,25 +258,87 @@ template <typename R> static BatchArgs<R> batch_args(ssgp_batch b, void *pool, i
     return a;
 }
 
+// The arguments of one group's phase launches: its item lists.
+template <typename R>
+static BatchArgs<R> batch_args_group(ssgp_batch b, void *pool, int nsteps, const BatchGroup &g) {
+    BatchArgs<R> a = batch_args<R>(b, pool, nsteps);
+    const int *L = b->gitems.as<int>();
+    a.x_items = L + g.xoff;
+    a.nrows = g.nrows;
+    a.nrows2 = g.nrows2;
+    a.y_items = L + g.yoff;
+    a.nyitems = g.nyitems;
+    a.r_items = L + g.roff;
+    a.ninst = g.ninst;
+    return a;
+}
+
+// nsteps steps of the rows, tiles and instances in `a` by one launch per phase.
+template <typename R> static int batch_enqueue_phases(hipStream_t st, const BatchArgs<R> &a, int nsteps) {
+    for (int s = 0; s < nsteps; ++s) {
+        LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_X, s > 0 ? 1 : 0));
+        LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_Y, 0));
+        LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_R, 0));
+    }
+    LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_SCALE, 0));
+    return SSGP_OK;
+}
+
 // Enqueues nsteps steps of the pool at `pool` in launch shape `shape`.
 template <typename R> static int batch_enqueue(ssgp_batch b, hipStream_t st, void *pool, int nsteps, int shape) {
     if (nsteps <= 0) return SSGP_OK;
-    const BatchArgs<R> a = batch_args<R>(b, pool, nsteps);
-    if (shape > 0) LAUNCH_TRY(launch_batch_reset(st, b->bar.as<unsigned>()));
     if (shape > 0) {
-        LAUNCH_TRY(launch_batch_persistent<R>(st, a, shape * b->ncu));
-    } else {
-        for (int s = 0; s < nsteps; ++s) {
-            LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_X, s > 0 ? 1 : 0));
-            LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_Y, 0));
-            LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_R, 0));
-        }
-        LAUNCH_TRY(launch_batch_phase<R>(st, a, BATCH_PHASE_SCALE, 0));
+        LAUNCH_TRY(launch_batch_reset(st, b->bar.as<unsigned>()));
+        LAUNCH_TRY(launch_batch_persistent<R>(st, batch_args<R>(b, pool, nsteps), shape * b->ncu));
+        return SSGP_OK;
+    }
+    if (shape == -1) return batch_enqueue_phases<R>(st, batch_args<R>(b, pool, nsteps), nsteps);
+    // groups: group 0 on st, group g on side[g - 1], forked from st and
+    // joined back into it (under stream capture: parallel branches)
+    const int lv = batch_group_level(shape);
+    if (lv == 0) return fail(SSGP_EINVAL, "unknown launch shape %d", shape);
+    const std::vector<BatchGroup> &gs = b->grouped[lv - 1];
+    if (gs.empty()) return fail(SSGP_EINVAL, "launch shape %d needs at least %d instances", shape, -shape);
+    HIP_TRY(hipEventRecord(b->evf, st));
+    for (size_t g = 1; g < gs.size(); ++g) HIP_TRY(hipStreamWaitEvent(b->side[g - 1], b->evf, 0));
+    int rc = SSGP_OK;
+    for (size_t g = 0; g < gs.size() && rc == SSGP_OK; ++g)
+        rc = batch_enqueue_phases<R>(g == 0 ? st : b->side[g - 1], batch_args_group<R>(b, pool, nsteps, gs[g]), nsteps);
+    // joined even after a failed launch, so that no side stream is left forked
+    for (size_t g = 1; g < gs.size(); ++g) {
+        if (hipEventRecord(b->evj[g - 1], b->side[g - 1]) != hipSuccess ||
+            hipStreamWaitEvent(st, b->evj[g - 1], 0) != hipSuccess)
+            if (rc == SSGP_OK) rc = fail(SSGP_EDEVICE, "joining the group streams failed");
+    }
+    return rc;
+}
+
+// nsteps steps of the pool at `pool` in launch shape `shape`, captured and
+// instantiated as a graph.
+template <typename R>
+static int batch_capture(ssgp_batch b, void *pool, int nsteps, int shape, hipGraphExec_t *out) {
+    *out = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = batch_enqueue<R>(b, b->cap, pool, nsteps, shape);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &graph);
+    if (rc != SSGP_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        SSGP_TRY(rc);
+        return fail(SSGP_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    }
+    const hipError_t e2 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+        *out = nullptr;
+        return fail(SSGP_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e2));
     }
     return SSGP_OK;
 }
 
-// Times every launch shape on a scratch copy of the pool; keeps the fastest.
+// Times every launch shape on a scratch copy of the pool, as the graph
+// replays it will run as (eager launches would charge the grouped shapes
+// their host launch time); keeps the fastest.
 template <typename R> static int batch_tune(ssgp_batch b) {
     DevBuf scratch;
     SSGP_TRY(scratch.ensure(b->pool_bytes));
@@ -205,18 +350,21 @@ template <typename R> static int batch_tune(ssgp_batch b) {
         return fail(SSGP_EDEVICE, "hipEventCreate failed");
     }
     std::vector<int> shapes = {-1};
+    for (int k = 1; k <= BATCH_GROUP_LEVELS; ++k)
+        if (!b->grouped[k - 1].empty()) shapes.push_back(-(1 << k));
     for (int k = 1; k <= b->occ; ++k) shapes.push_back(k);
-    const int steps = 4, reps = 3;
+    const int steps = 8, reps = 3;
     int best = 0;
     double best_us = 0.0;
     int rc = SSGP_OK;
     for (int shape : shapes) {
         double t_min = 1e300;
+        hipGraphExec_t exec = nullptr;
+        rc = batch_capture<R>(b, scratch.p, steps, shape, &exec);
         for (int r = 0; r <= reps && rc == SSGP_OK; ++r) {  // r = 0 warms up
-            rc = batch_enqueue<R>(b, b->stream, scratch.p, steps, shape);
-            if (rc != SSGP_OK) break;
             if (hipEventRecord(e0, b->stream) != hipSuccess) rc = fail(SSGP_EDEVICE, "hipEventRecord failed");
-            if (rc == SSGP_OK) rc = batch_enqueue<R>(b, b->stream, scratch.p, steps, shape);
+            if (rc == SSGP_OK && hipGraphLaunch(exec, b->stream) != hipSuccess)
+                rc = fail(SSGP_EDEVICE, "hipGraphLaunch failed");
             if (rc == SSGP_OK && hipEventRecord(e1, b->stream) != hipSuccess)
                 rc = fail(SSGP_EDEVICE, "hipEventRecord failed");
             if (rc == SSGP_OK && hipEventSynchronize(e1) != hipSuccess)
@@ -226,6 +374,7 @@ template <typename R> static int batch_tune(ssgp_batch b) {
                 rc = fail(SSGP_EDEVICE, "hipEventElapsedTime failed");
             if (rc == SSGP_OK && r > 0) t_min = std::min(t_min, 1e3 * ms / steps);
         }
+        if (exec) (void)hipGraphExecDestroy(exec);
         if (rc != SSGP_OK) break;
         if (best == 0 || t_min < best_us) {
             best = shape;
@@ -246,19 +395,7 @@ template <typename R> static int batch_tune(ssgp_batch b) {
 
 template <typename R> static int batch_graph(ssgp_batch b, int lg, hipGraphExec_t *out) {
     if ((int)b->graphs.size() <= lg) b->graphs.resize(lg + 1, nullptr);
-    if (!b->graphs[lg]) {
-        HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-        const int rc = batch_enqueue<R>(b, b->cap, b->pool, 1 << lg, b->shape);
-        hipGraph_t graph = nullptr;
-        const hipError_t e = hipStreamEndCapture(b->cap, &graph);
-        SSGP_TRY(rc);
-        if (e != hipSuccess) return fail(SSGP_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
-        hipGraphExec_t exec = nullptr;
-        const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e2 != hipSuccess) return fail(SSGP_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e2));
-        b->graphs[lg] = exec;
-    }
+    if (!b->graphs[lg]) SSGP_TRY(batch_capture<R>(b, b->pool, 1 << lg, b->shape, &b->graphs[lg]));
     *out = b->graphs[lg];
     return SSGP_OK;
 }
@@ -325,6 +462,12 @@ extern "C" int ssgp_create_batch(int n, const int *nx, const int *ny, const doub
     if (rc == SSGP_OK) b->ncu = b->grids[0]->ncu;
     if (rc == SSGP_OK && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
         rc = fail(SSGP_EDEVICE, "hipStreamCreateWithFlags failed");
+    for (int g = 0; g < BATCH_MAX_GROUPS - 1 && rc == SSGP_OK; ++g)
+        if (hipStreamCreateWithFlags(&b->side[g], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->evj[g], hipEventDisableTiming) != hipSuccess)
+            rc = fail(SSGP_EDEVICE, "creating the group streams failed");
+    if (rc == SSGP_OK && hipEventCreateWithFlags(&b->evf, hipEventDisableTiming) != hipSuccess)
+        rc = fail(SSGP_EDEVICE, "hipEventCreateWithFlags failed");
     if (rc == SSGP_OK) rc = dtype == SSGP_C128 ? batch_build<double>(b, offsets) : batch_build<float>(b, offsets);
     if (rc != SSGP_OK) {
         delete b;
@@ -349,8 +492,12 @@ extern "C" int ssgp_batch_step_imag_serial(ssgp_batch b, int nsteps) {
 
 extern "C" int ssgp_batch_set_shape(ssgp_batch b, int shape) {
     if (!b) return fail(SSGP_EINVAL, "batch is NULL");
-    if (shape < -1 || shape > b->occ)
-        return fail(SSGP_EINVAL, "shape must be -1, 0 or a workgroup count in [1, %d] per compute unit", b->occ);
+    const int lv = batch_group_level(shape);
+    if ((shape < -1 && lv == 0) || shape > b->occ)
+        return fail(SSGP_EINVAL, "shape must be -4, -2, -1, 0 or a workgroup count in [1, %d] per compute unit",
+                    b->occ);
+    if (lv > 0 && b->grouped[lv - 1].empty())
+        return fail(SSGP_EINVAL, "launch shape %d needs at least %d instances", shape, -shape);
     if (shape != b->shape) {
         HIP_TRY(hipStreamSynchronize(b->stream));
         b->drop_graphs();

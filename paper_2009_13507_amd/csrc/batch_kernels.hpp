@@ -65,6 +65,7 @@ template <typename R> struct BatchArgs {
     double *partials;          // [total tiles][3] tile sums of |psi|^2
     double *renorm;            // [instances][8]: d[3], N[3], fallback
     int ninst;
+    const int *r_items;        // instances of the R phase (nullptr: 0 .. ninst - 1)
     unsigned *bar;             // [0] arrivals, [1] generation, [2] stop, [3] sticky timeout flag
     int nsteps;
     long long spin_limit;
@@ -688,7 +689,7 @@ __global__ void __launch_bounds__(BATCH_THREADS) batch_y_kernel(BatchArgs<R> a) 
 template <typename R>
 __global__ void __launch_bounds__(BATCH_THREADS) batch_renorm_kernel(BatchArgs<R> a) {
     __shared__ BatchSmem<R> S;
-    batch_renorm_item(a, blockIdx.x, S);
+    batch_renorm_item(a, a.r_items ? a.r_items[blockIdx.x] : (int)blockIdx.x, S);
 }
 
 template <typename R>

@@ -70,7 +70,7 @@ def oracle_run(k, psi0, nsteps):
     return oracle.step(cfg, psi0, nsteps)
 
 
-@pytest.mark.parametrize("shape", [-1, 1, "max"])
+@pytest.mark.parametrize("shape", [-1, -2, -4, 1, "max"])
 def test_batch_matches_oracle(shape):
     b = make_ragged()
     b.set_shape(b.info()["max_per_cu"] if shape == "max" else shape)
@@ -85,7 +85,7 @@ def test_batch_matches_oracle(shape):
 def test_every_shape_gives_identical_bits():
     ref = None
     b0 = make_ragged()
-    shapes = [-1] + list(range(1, b0.info()["max_per_cu"] + 1))
+    shapes = [-1, -2, -4] + list(range(1, b0.info()["max_per_cu"] + 1))
     b0.close()
     for shape in shapes:
         b = make_ragged()
@@ -101,12 +101,13 @@ def test_every_shape_gives_identical_bits():
         b.close()
 
 
-def test_split_runs_give_identical_bits():
+@pytest.mark.parametrize("shape", [1, -4])
+def test_split_runs_give_identical_bits(shape):
     a = make_ragged()
-    a.set_shape(1)
+    a.set_shape(shape)
     a.step_imag(11)
     b = make_ragged()
-    b.set_shape(1)
+    b.set_shape(shape)
     b.step_imag(3)
     b.step_imag(6)
     b.step_imag(2)
@@ -121,7 +122,7 @@ def test_autotuner_picks_a_timed_shape():
     b.step_imag(5)
     b.sync()
     info = b.info()
-    assert info["shape"] == -1 or 1 <= info["shape"] <= info["max_per_cu"]
+    assert info["shape"] in (-1, -2, -4) or 1 <= info["shape"] <= info["max_per_cu"]
     assert info["us_per_step"] > 0
     ref = make_ragged()
     ref.set_shape(-1)
@@ -170,8 +171,33 @@ def test_bad_shape_is_rejected():
     b = make_ragged()
     with pytest.raises(api.SSGPError):
         b.set_shape(b.info()["max_per_cu"] + 1)
+    for bad in (-3, -5, -8):
+        with pytest.raises(api.SSGPError):
+            b.set_shape(bad)
+    b.close()
+
+
+def test_groups_need_as_many_instances():
+    """Shapes -2 and -4 split the instances into groups: a batch with fewer
+    instances than groups rejects the shape, and the tuner does not time it."""
+    states, dxs, prm = ragged_states()[:3], [r[2] for r in RAGGED[:3]], ragged_params()[:3]
+    b = api.Batch.from_states(states, dxs, prm)
+    b.set_shape(-2)
     with pytest.raises(api.SSGPError):
-        b.set_shape(-2)
+        b.set_shape(-4)
+    b.set_shape(0)
+    b.step_imag(3)
+    b.sync()
+    assert b.info()["shape"] != -4
+    got = snapshot(b)
+    for k, psi0 in enumerate(states):
+        assert rel(got[k], oracle_run(k, psi0, 3)) < TOL, k
+    one = api.Batch.from_states(states[:1], dxs[:1], prm[:1])
+    with pytest.raises(api.SSGPError):
+        one.set_shape(-2)
+    one.set_shape(-1)
+    one.close()
+    b.close()
 
 
 # ------------------------------------------------ the 64-instance workload --
