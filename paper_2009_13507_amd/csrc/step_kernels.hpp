@@ -832,8 +832,8 @@ __device__ __forceinline__ void wave_exchange(cx<R> *line, int lane, const cx<R>
 
 template <typename R, int KM, bool FULL>
 __device__ __forceinline__ void store_row(cx<R> *dst, long long plane, int nx, const cx<R> (&r)[3][KM],
-                                          cx<R> *line) {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                                          cx<R> *line, int w) {
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const int wbase = 64 * KM * w;
     if constexpr (KM == 1) {
 #pragma unroll
@@ -864,7 +864,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     auto &scA = sh.scA;
     auto &scB = sh.scB;
     const int nx = FULL ? XPASS_THREADS * KM : a.nx;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int i0 = tid * KM;  // this thread's points: i0 .. i0 + KM - 1
     const long long roff = (long long)row * nx;
 
@@ -1112,7 +1112,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     } else {
         bwd_fix3<R, KM>(r, len, cpl, carry);
     }
-    store_row<R, KM, FULL>(dst, a.plane, nx, r, sh.xch[w]);
+    store_row<R, KM, FULL>(dst, a.plane, nx, r, sh.xch[w], w);
 }
 
 // (The unitary-SO form holds three coefficient sets per thread: with
