@@ -338,7 +338,8 @@ static int batch_capture(ssgp_batch b, void *pool, int nsteps, int shape, hipGra
 
 // Times every launch shape on a scratch copy of the pool, as the graph
 // replays it will run as (eager launches would charge the grouped shapes
-// their host launch time); keeps the fastest.
+// their host launch time): the fastest of 5 replays of 16 steps after a
+// warm-up replay.  Keeps the fastest shape.
 template <typename R> static int batch_tune(ssgp_batch b) {
     DevBuf scratch;
     SSGP_TRY(scratch.ensure(b->pool_bytes));
@@ -353,7 +354,7 @@ template <typename R> static int batch_tune(ssgp_batch b) {
     for (int k = 1; k <= BATCH_GROUP_LEVELS; ++k)
         if (!b->grouped[k - 1].empty()) shapes.push_back(-(1 << k));
     for (int k = 1; k <= b->occ; ++k) shapes.push_back(k);
-    const int steps = 8, reps = 3;
+    const int steps = 16, reps = 5;  // shapes within 2% of each other need the longer sample
     int best = 0;
     double best_us = 0.0;
     int rc = SSGP_OK;
