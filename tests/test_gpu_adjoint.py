@@ -78,16 +78,20 @@ def test_adjoint_steps_match_oracle(dim, nx, ny, so):
     g.close()
 
 
-def test_autograd_with_checkpoints_matches_oracle():
+@pytest.mark.parametrize("every", [4, 1, 7, 19])
+def test_autograd_with_checkpoints_matches_oracle(every):
+    """Checkpoints every 4 steps (5 segments, the last partial: the two
+    segment buffers of the backward pass reused in turn), every step (no
+    recomputation), every 7 (3 segments) and one segment (one buffer)."""
     nx, ny, dx = 48, 40, 0.3
     base = base_cfg(2, nx, ny, dx)
     sched = [0.1, 0.2, 0.05, 0.3]
-    sps, steps = 5, 19     # 4 segments, the last partial; checkpoints every 4 steps
+    sps, steps = 5, 19     # 4 Omega segments, the last partial
     psi0 = start(2, nx, ny, dx, 2)
     psiT_ref, _, lam_ref, dom_ref = oracle_chain(psi0, sched, sps, steps, base)
     prob = autograd.RealTimeProblem(dx=dx, dy=dx, dt=base["dt"], steps=steps, steps_per_seg=sps,
                                     c0=base["c0"], c2=base["c2"], gamma=base["gamma"], so=base["so"],
-                                    checkpoint=4)
+                                    checkpoint=every)
     p0 = torch.from_numpy(psi0.copy()).to(DEV).requires_grad_(True)
     om = torch.tensor(sched, dtype=torch.float64, device=DEV, requires_grad=True)
     psiT = autograd.propagate(p0, om, prob)
