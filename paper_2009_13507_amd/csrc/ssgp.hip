@@ -444,7 +444,7 @@ template <typename R> static int build_uso(ssgp_grid g, int mode, int L, int nch
     CNHost tab[3];
     std::vector<cx<R>> ramp((size_t)g->nx);
     int levels = 1;
-    cd rho0 = 1.0;
+    cd rho0 = 1.0, o0 = 0.0;
     for (int c = 0; c < 3; ++c) {
         const cd u = s * (-0.5 / (h * h) - I * gam * lam[c] / (2.0 * h));
         cd rho = 1.0;
@@ -459,6 +459,16 @@ template <typename R> static int build_uso(ssgp_grid g, int mode, int L, int nch
         const cd o = u * rho;
         if (!(std::abs(d) > 2.0 * std::abs(o)))
             return fail(SSGP_EINVAL, "unitary SO: the line matrix is not diagonally dominant (dt gamma too large)");
+        if (c == 2) {
+            // o_c^2 = u_c l_c = s^2 (1/(4h^4) + (gamma lambda_c / 2h)^2), and with
+            // rho_2 = conj(rho_0), o_2 / o_0 = (l_0 / u_0) (u_0 / l_0) = 1: line 2
+            // has line 0's matrix, so it takes line 0's tables (the kernels
+            // solve both with one coefficient set)
+            if (std::abs(o - o0) > 1e-12 * std::abs(o0)) return fail(SSGP_EDEVICE, "unitary SO: lines 0 and 2 differ");
+            tab[2] = tab[0];
+            continue;
+        }
+        if (c == 0) o0 = o;
         tab[c] = cn_tables_do(g->nx, d, o, (2.0 - d) / o, L, nchunks, 6);
         levels = std::max(levels, tab[c].levels);
     }

@@ -628,8 +628,11 @@ template <typename R> struct XArgs {
     // term is solved together with CN_x.  In the eigenbasis of the SO spin
     // matrix component c is a tridiagonal Toeplitz system with off-diagonals
     // of equal modulus; the diagonal similarity by unit phases (the ramp of
-    // line c) makes it symmetric, and it is solved like CN_x with its own
-    // tables cu[c] and rdiag_u[c].  The basis change: uso_in / uso_out.
+    // line c) makes it symmetric, and it is solved like CN_x with the tables
+    // cu[c] and rdiag_u[c].  Lines 0 and 2 (eigenvalues lambda and -lambda)
+    // then have the same matrix: the kernels solve line 2 with line 0's
+    // tables (cu[2] and rdiag_u[2] are left unread).  The basis change:
+    // uso_in / uso_out.
     const cx<R> *ramp;         // [nx]: the ramp of line 0, or nullptr: the paper's scheme
     R rotr[9];                 // Wr (row j: component, column c: eigenvector)
     int rotp[3];               // the phase of row j: i^rotp[j]
@@ -1006,7 +1009,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
         for (int k = 0; k < KM; ++k) {
             const cx<R> pu = k > 0 ? u[j][k > 0 ? k - 1 : 0] : ub[j];
             const cx<R> nu = k + 1 < KM ? u[j][k + 1 < KM ? k + 1 : 0] : ua[j];
-            r[j][k] = (FULL || i0 + k < nx) ? cn_rhs(USO ? (P2 ? a.ul->rdiag_u[j] : a.rdiag_u[j]) : a.rdiag, u[j][k], pu + nu)
+            r[j][k] = (FULL || i0 + k < nx) ? cn_rhs(USO ? (P2 ? a.ul->rdiag_u[j & 1] : a.rdiag_u[j & 1]) : a.rdiag, u[j][k], pu + nu)
                                             : czero<R>();
         }
     }
@@ -1018,7 +1021,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     const LineCoef<R> *ucf = P2 ? a.ul->cu : a.cu;
     const ChunkCoef<R, KM, CM> cpl(USO ? ucf[0] : a.cx_, i0);
     const ChunkCoef<R, KM, CM> cpl1(USO ? ucf[1] : a.cx_, i0);
-    const ChunkCoef<R, KM, CM> cpl2(USO ? ucf[2] : a.cx_, i0);
+    const ChunkCoef<R, KM, CM> cpl2(USO ? ucf[0] : a.cx_, i0);  // (USO: line 2 has line 0's matrix)
     auto coef = [&](int j) -> const ChunkCoef<R, KM, CM> & { return j == 0 ? cpl : j == 1 ? cpl1 : cpl2; };
     const cx<R> Ak = a.cx_.chunkA[tid];
     const int levels = USO ? ucf[0].levels : a.cx_.levels;  // (USO: the host gives the three the same)
@@ -1026,7 +1029,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     // forward sweep: chunk eliminations, scan, carries across wavefronts
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        A[j] = USO ? ucf[j].chunkA[tid] : Ak;
+        A[j] = USO ? ucf[j & 1].chunkA[tid] : Ak;
         B[j] = fwd_local<R, KM>(r[j], len, USO ? coef(j) : cpl);
     }
     wave_scan_up3<R>(A, B, levels);
@@ -1065,7 +1068,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     // back substitution: chunk sweeps, reverse scan, carries
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        A[j] = USO ? ucf[j].chunkA[tid] : Ak;
+        A[j] = USO ? ucf[j & 1].chunkA[tid] : Ak;
         B[j] = bwd_local<R, KM>(r[j], len, USO ? coef(j) : cpl);
     }
     wave_scan_down3<R>(A, B, levels);
