@@ -624,6 +624,14 @@ template <typename R> struct XArgs {
     cx<R> rdiag;               // diagonal of (I - sT)/o (off-diagonal -1)
     cx<R> qx[9];               // SO: psi'_j += sum_j' qx[j][j'] (psi_j'(i+1) - psi_j'(i-1))
     unsigned qxmask;           // bit 3j+j' set where qx[j][j'] != 0
+    // What the x-pass reads of qx (set by its launcher): the 2D grids' x
+    // derivative SO terms (gamma p_x S_x, and the equal mixture's -gamma p_x
+    // S_y) couple neighbouring components only, with qx[0][1] = qx[1][2] =: qa
+    // and qx[1][0] = qx[2][1] =: qb (sopat 1); sopat 0: no SO terms.  Two
+    // coefficients instead of nine keep the pass's scalar registers from
+    // spilling.
+    int sopat;
+    cx<R> qa, qb;
     // Unitary-SO scheme (x-derivative SO forms; no qx terms then): the SO
     // term is solved together with CN_x.  In the eigenbasis of the SO spin
     // matrix component c is a tridiagonal Toeplitz system with off-diagonals
@@ -965,21 +973,22 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int k = 0; k < KM; ++k) u[j][k] = v[j][k];
-    // one coefficient at a time over the thread's points (the terms of each
-    // point are still added in the order jp = 0, 1, 2)
+    // the terms of each point in the order j' = 0, 1, 2 of the sum over j'
+    if (a.sopat != 0) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < KM; ++k) {
+            cx<R> d[3];  // psi_j'(i+1) - psi_j'(i-1)
 #pragma unroll
-        for (int jp = 0; jp < 3; ++jp)
-            if (a.qxmask & (1u << (3 * j + jp))) {
-                const cx<R> q = a.qx[3 * j + jp];
-#pragma unroll
-                for (int k = 0; k < KM; ++k) {
-                    const cx<R> pv = k > 0 ? v[jp][k > 0 ? k - 1 : 0] : vb[jp];
-                    const cx<R> nv = k + 1 < KM ? v[jp][k + 1 < KM ? k + 1 : 0] : va[jp];
-                    u[j][k] = cfma(q, nv - pv, u[j][k]);
-                }
+            for (int jp = 0; jp < 3; ++jp) {
+                const cx<R> pv = k > 0 ? v[jp][k > 0 ? k - 1 : 0] : vb[jp];
+                const cx<R> nv = k + 1 < KM ? v[jp][k + 1 < KM ? k + 1 : 0] : va[jp];
+                d[jp] = nv - pv;
             }
+            u[0][k] = cfma(a.qa, d[1], u[0][k]);
+            u[1][k] = cfma(a.qa, d[2], cfma(a.qb, d[0], u[1][k]));
+            u[2][k] = cfma(a.qb, d[1], u[2][k]);
+        }
+    }
 #pragma unroll
     for (int k = 0; k < KM; ++k)
         if (!FULL && i0 + k >= nx)
@@ -990,7 +999,7 @@ __device__ __forceinline__ void xpass_row(const XArgs<R> &a, int row, cx<R> (&v)
     // forms after their pointwise + SO pass, no coupling) u is v, whose outer
     // values are at hand: no second exchange
     cx<R> ub[3], ua[3];  // u just before and just after this thread's points
-    if (!USO && a.qxmask == 0) {  // (the unitary-SO pass keeps the exchange: it measured faster so)
+    if (!USO && a.sopat == 0) {  // (the unitary-SO pass keeps the exchange: it measured faster so)
 #pragma unroll
         for (int jj = 0; jj < 3; ++jj) {
             ub[jj] = vb[jj];

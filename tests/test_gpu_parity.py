@@ -60,8 +60,11 @@ SHAPES_2D = [(96, 80), (37, 29), (130, 67), (64, 64), (1, 7), (5, 1), (200, 3), 
 
 @pytest.mark.parametrize("nx,ny", SHAPES_2D)
 @pytest.mark.parametrize("imag", [False, True])
-@pytest.mark.parametrize("so", [api.SO_NONE, api.SO_PX_SX])
+@pytest.mark.parametrize("so", [api.SO_NONE, api.SO_PX_SX, api.SO_ERD])
 def test_2d_steps_match_oracle(nx, ny, imag, so):
+    """The 2D x-derivative SO terms: gamma p_x S_x (the two coefficient
+    values of the x-pass equal) and the equal mixture's -gamma p_x S_y
+    (opposite values)."""
     dx, dy = 0.25, 0.3
     p = dict(c0=3.0, c2=-0.7, gamma=0.6 if so else 0.0, omega=0.25, dt=2e-3, so=so)
     psi0 = start_state(2, nx, ny, dx, dy)
