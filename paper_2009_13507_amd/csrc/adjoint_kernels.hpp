@@ -156,6 +156,8 @@ template <typename R> struct AdjXArgs {
     cx<R> rdiag;               // diagonal of (I - sT)/o (off-diagonal -1)
     cx<R> qx[9];               // SO^H stencil couplings
     unsigned qxmask;
+    int sopat;                 // what the kernel reads of qx (set by its launcher, so_pattern):
+    cx<R> qa, qb;              // 1 neighbouring components, 2 diagonal, 0 none
     double *omega_partials;    // [ny] per-row Omega derivative
 };
 
@@ -223,17 +225,23 @@ __global__ void __launch_bounds__(ADJ_THREADS) adj_xpass_kernel(AdjXArgs<R> a) {
         cx<R> g[3], p[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            cx<R> v = s[j * ld + sidx<L>(i)];
-#pragma unroll
-            for (int jp = 0; jp < 3; ++jp) {
-                if (a.qxmask & (1u << (3 * j + jp))) {
-                    const cx<R> fp = i + 1 < nx ? s[jp * ld + sidx<L>(i + 1)] : czero<R>();
-                    const cx<R> fm = i >= 1 ? s[jp * ld + sidx<L>(i - 1)] : czero<R>();
-                    v = cfma(a.qx[3 * j + jp], fp - fm, v);
-                }
-            }
-            g[j] = v;
+            g[j] = s[j * ld + sidx<L>(i)];
             p[j] = psi[j * a.plane + i];
+        }
+        // SO^H: the terms of each component in the order j' = 0, 1, 2
+        auto diff = [&](int jp) {
+            const cx<R> fp = i + 1 < nx ? s[jp * ld + sidx<L>(i + 1)] : czero<R>();
+            const cx<R> fm = i >= 1 ? s[jp * ld + sidx<L>(i - 1)] : czero<R>();
+            return fp - fm;
+        };
+        if (a.sopat == 1) {
+            const cx<R> d0 = diff(0), d1 = diff(1), d2 = diff(2);
+            g[0] = cfma(a.qa, d1, g[0]);
+            g[1] = cfma(a.qa, d2, cfma(a.qb, d0, g[1]));
+            g[2] = cfma(a.qb, d1, g[2]);
+        } else if (a.sopat == 2) {
+            g[0] = cfma(a.qa, diff(0), g[0]);
+            g[2] = cfma(a.qb, diff(2), g[2]);
         }
         const R xv = a.x0 + R(i) * a.dx;
         dom += (double)pointwise_adjoint_real(p, g, R(0.5) * xv * xv + vy, a.m);

@@ -5,6 +5,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "adjoint_kernels.hpp"
 #include "batch_kernels.hpp"
 #include "obs_kernels.hpp"
@@ -30,6 +32,32 @@ inline hipError_t launch_timed(const Launch &c, K kern, dim3 grid, dim3 block, s
     }
     void *argv[] = {(void *)&args};
     return hipExtLaunchKernel((const void *)kern, grid, block, argv, lds, c.stream, c.ev_start, c.ev_stop, 0);
+}
+
+// The SO coefficient pattern of a row kernel's arguments (sopat, qa, qb)
+// from qx and qxmask.  The x-derivative SO forms give one of two: sopat 1
+// (S_x, S_y, the equal mixture) couples neighbouring components, with
+// qa = qx[0][1] = qx[1][2] and qb = qx[1][0] = qx[2][1]; sopat 2 (S_z) is
+// diagonal, qa = qx[0][0], qb = qx[2][2]; sopat 0: no SO terms.  Compared
+// bitwise, so that a kernel adds the same numbers as the sum over all nine
+// entries would; false for another pattern (no SO form gives one).
+template <typename A> inline bool so_pattern(A &a) {
+    auto same = [](const auto &p, const auto &q) { return std::memcmp(&p, &q, sizeof p) == 0; };
+    a.sopat = 0;
+    if (a.qxmask == 0) return true;
+    if (a.qxmask == 0xAAu && same(a.qx[1], a.qx[5]) && same(a.qx[3], a.qx[7])) {  // (0,1) (1,0) (1,2) (2,1)
+        a.sopat = 1;
+        a.qa = a.qx[1];
+        a.qb = a.qx[3];
+        return true;
+    }
+    if (a.qxmask == 0x101u) {  // (0,0) (2,2)
+        a.sopat = 2;
+        a.qa = a.qx[0];
+        a.qb = a.qx[8];
+        return true;
+    }
+    return false;
 }
 
 // Dynamic LDS of the 1D and adjoint row kernels: all three components.

@@ -50,8 +50,13 @@ def start(dim, nx, ny, dx, seed):
 
 @pytest.mark.parametrize("dim,nx,ny,so", [(2, 40, 33, api.SO_PX_SX), (2, 130, 70, api.SO_PX_SX),
                                           (2, 300, 17, api.SO_PX_SX), (1, 200, 1, api.SO_PX_SX),
-                                          (1, 600, 1, api.SO_PX_SX), (2, 64, 40, api.SO_ERD)])
+                                          (1, 600, 1, api.SO_PX_SX), (2, 64, 40, api.SO_ERD),
+                                          (1, 200, 1, api.SO_PX_SY), (1, 200, 1, api.SO_PX_SZ),
+                                          (2, 40, 33, api.SO_NONE)])
 def test_adjoint_steps_match_oracle(dim, nx, ny, so):
+    """Every SO coefficient pattern of the adjoint x-pass: neighbouring
+    components with equal (S_x) or opposite (S_y, the equal mixture)
+    coefficients, the diagonal (S_z), none."""
     dx = 0.3 if dim == 2 else 0.1
     base = base_cfg(dim, nx, ny, dx, so=so)
     sched = [0.05, 0.25, 0.12]
