@@ -266,11 +266,8 @@ int ssgp_create_batch(int n, const int *nx, const int *ny, const double *dx,
 /* nsteps imaginary-time steps of every grid of the batch; each grid is
  * normalised on return.  The steps run as graphs of 2^i steps (HIP graphs,
  * captured on first use) of the batch's launch shape: one persistent kernel
- * with device-wide barriers between the x and y sweeps, one kernel launch
- * per sweep over all grids, or the grids in 2 or 4 groups, each group's
- * launches on a stream of its own (created with the batch, default
- * priority; forked from and joined back into the batch's stream, so the
- * call still orders on that stream alone).  The first call times every shape on a scratch
+ * with device-wide barriers between the x and y sweeps, or one kernel
+ * launch per sweep over all grids.  The first call times every shape on a scratch
  * copy of the pool (allocated for the duration of the tuning) unless
  * ssgp_batch_set_shape fixed one; results do not depend on the shape.  A
  * barrier wait that times out ends the kernel (every workgroup leaves) and
@@ -284,9 +281,10 @@ int ssgp_batch_step_imag_serial(ssgp_batch b, int nsteps);
 
 /* Launch shape of ssgp_batch_step_imag: k > 0 is the persistent kernel with
  * k workgroups per compute unit (at most out[2] of ssgp_batch_info), -1 one
- * kernel launch per sweep, -2 and -4 the grids in 2 or 4 groups of about
- * equal points with one launch per sweep and group (SSGP_EINVAL with fewer
- * grids than groups), 0 re-runs the autotuner at the next step call.
+ * kernel launch per sweep, 0 re-runs the autotuner at the next step call.
+ * -2 and -4 (the grids in 2 or 4 groups of about equal points, one launch
+ * per sweep and group, each group on its own stream) are switched off in
+ * this build: SSGP_EINVAL, and the autotuner does not time them.
  * Synchronises the stream when the shape changes. */
 int ssgp_batch_set_shape(ssgp_batch b, int shape);
 

@@ -251,9 +251,9 @@ class Batch:
 
     def set_shape(self, shape: int):
         """k > 0: persistent kernel, k workgroups per compute unit; -1: one
-        launch per sweep; -2, -4: the grids in 2 or 4 groups, one launch per
-        sweep and group, each group on its own stream; 0: autotune at the
-        next step call."""
+        launch per sweep; 0: autotune at the next step call.  (-2 and -4, the
+        grids in groups on streams of their own, are switched off: the
+        library refuses them.)"""
         check(self._lib.ssgp_batch_set_shape(self._h, int(shape)))
 
     def info(self) -> dict:
