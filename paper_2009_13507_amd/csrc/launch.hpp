@@ -41,24 +41,25 @@ inline hipError_t launch_timed(const Launch &c, K kern, dim3 grid, dim3 block, s
 // diagonal, qa = qx[0][0], qb = qx[2][2]; sopat 0: no SO terms.  Compared
 // bitwise, so that a kernel adds the same numbers as the sum over all nine
 // entries would; false for another pattern (no SO form gives one).
-template <typename A> inline bool so_pattern(A &a) {
-    auto same = [](const auto &p, const auto &q) { return std::memcmp(&p, &q, sizeof p) == 0; };
-    a.sopat = 0;
-    if (a.qxmask == 0) return true;
-    if (a.qxmask == 0xAAu && same(a.qx[1], a.qx[5]) && same(a.qx[3], a.qx[7])) {  // (0,1) (1,0) (1,2) (2,1)
-        a.sopat = 1;
-        a.qa = a.qx[1];
-        a.qb = a.qx[3];
+template <typename C> inline bool so_pattern_of(const C (&q)[9], unsigned mask, int &pat, C &qa, C &qb) {
+    auto same = [](const C &p, const C &r) { return std::memcmp(&p, &r, sizeof p) == 0; };
+    pat = 0;
+    if (mask == 0) return true;
+    if (mask == 0xAAu && same(q[1], q[5]) && same(q[3], q[7])) {  // (0,1) (1,0) (1,2) (2,1)
+        pat = 1;
+        qa = q[1];
+        qb = q[3];
         return true;
     }
-    if (a.qxmask == 0x101u) {  // (0,0) (2,2)
-        a.sopat = 2;
-        a.qa = a.qx[0];
-        a.qb = a.qx[8];
+    if (mask == 0x101u) {  // (0,0) (2,2)
+        pat = 2;
+        qa = q[0];
+        qb = q[8];
         return true;
     }
     return false;
 }
+template <typename A> inline bool so_pattern(A &a) { return so_pattern_of(a.qx, a.qxmask, a.sopat, a.qa, a.qb); }
 
 // Dynamic LDS of the 1D and adjoint row kernels: all three components.
 template <typename R> inline size_t row_lds(int nx, int L) { return (size_t)3 * (nx + nx / L + 1) * sizeof(cx<R>); }

@@ -1378,6 +1378,12 @@ template <typename R> struct SOArgs {
     const double *dscale;      // RENORM factors to apply first, or nullptr
     cx<R> qx[9], qy[9];        // as in XArgs
     unsigned qxmask, qymask;
+    // what the kernel reads (set by its launcher): the y-derivative forms'
+    // x and y terms both couple neighbouring components (pattern 1 of
+    // XArgs::sopat), qxa = qx[0][1] = qx[1][2], qxb = qx[1][0] = qx[2][1],
+    // and likewise qya, qyb; xpat, ypat 0: no such terms
+    int xpat, ypat;
+    cx<R> qxa, qxb, qya, qyb;
 };
 
 constexpr int PSO_WAVES = 8, PSO_RPW = 2;  // wavefronts, rows per wavefront
@@ -1473,18 +1479,21 @@ __global__ void __launch_bounds__(64 * PSO_WAVES) __attribute__((amdgpu_waves_pe
             dn[jp] = k > 0 ? v[k > 0 ? k - 1 : 0][jp] : sh.yrow[2 * w][jp][lane];
             up[jp] = k < PSO_RPW - 1 ? v[k < PSO_RPW - 1 ? k + 1 : 0][jp] : sh.yrow[2 * w + 3][jp][lane];
         }
+        // each component's x terms, then its y terms, in the order j' = 0, 1, 2
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            u[j] = v[k][j];
-#pragma unroll
-            for (int jp = 0; jp < 3; ++jp)
-                if (a.qxmask & (1u << (3 * j + jp))) u[j] = cfma(a.qx[3 * j + jp], nv[jp] - pv[jp], u[j]);
+        for (int j = 0; j < 3; ++j) u[j] = v[k][j];
+        if (a.xpat) {
+            const cx<R> d0 = nv[0] - pv[0], d1 = nv[1] - pv[1], d2 = nv[2] - pv[2];
+            u[0] = cfma(a.qxa, d1, u[0]);
+            u[1] = cfma(a.qxa, d2, cfma(a.qxb, d0, u[1]));
+            u[2] = cfma(a.qxb, d1, u[2]);
         }
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int jp = 0; jp < 3; ++jp)
-                if (a.qymask & (1u << (3 * j + jp))) u[j] = cfma(a.qy[3 * j + jp], up[jp] - dn[jp], u[j]);
+        if (a.ypat) {
+            const cx<R> d0 = up[0] - dn[0], d1 = up[1] - dn[1], d2 = up[2] - dn[2];
+            u[0] = cfma(a.qya, d1, u[0]);
+            u[1] = cfma(a.qya, d2, cfma(a.qyb, d0, u[1]));
+            u[2] = cfma(a.qyb, d1, u[2]);
+        }
         const int y = yw + k;
         if (FULL || (x < a.nx && y < a.ny)) {
             const long long q = (long long)y * a.nx + x;
