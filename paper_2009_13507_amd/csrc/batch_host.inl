@@ -174,6 +174,8 @@ template <typename R> static int batch_build(ssgp_batch b, const long long *offs
         I.rdy = T.ly[i].rdiag;
         for (int q = 0; q < 9; ++q) I.qx[q] = xa.qx[q];
         I.qxmask = xa.qxmask;
+        if (!so_pattern_of(I.qx, I.qxmask, I.sopat, I.qa, I.qb) || I.sopat == 2)
+            return fail(SSGP_EINVAL, "instance %d: SO coefficients of an unexpected pattern", i);
         I.sp = renorm_spec(*g);
     }
     b->ntiles = tile_base;

@@ -52,8 +52,31 @@ template <typename R> struct BatchInst {
     cx<R> rdx, rdy;            // diagonal of (I - sT)/o of x and y (off-diagonal -1)
     cx<R> qx[9];               // SO: psi'_j += sum_j' qx[j][j'] (psi_j'(i+1) - psi_j'(i-1))
     unsigned qxmask;
+    int sopat;                 // what the row kernels read of qx (as XArgs::sopat): 1 neighbouring
+    cx<R> qa, qb;              // components (qa = qx[0][1] = qx[1][2], qb = qx[1][0] = qx[2][1]), 0 none
     RenormSpec sp;
 };
+
+// SO update of a row's L consecutive points from the two coefficients of
+// the neighbouring-component pattern (each component's terms in the order
+// j' = 0, 1, 2); vb, va: the values just before and after the points.
+template <typename R, int L>
+__device__ __forceinline__ void so_neighbours(cx<R> (&u)[3][L], const cx<R> (&v)[3][L], const cx<R> (&vb)[3],
+                                              const cx<R> (&va)[3], cx<R> qa, cx<R> qb) {
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        cx<R> d[3];
+#pragma unroll
+        for (int jp = 0; jp < 3; ++jp) {
+            const cx<R> pv = t > 0 ? v[jp][t > 0 ? t - 1 : 0] : vb[jp];
+            const cx<R> nv = t + 1 < L ? v[jp][t + 1 < L ? t + 1 : 0] : va[jp];
+            d[jp] = nv - pv;
+        }
+        u[0][t] = cfma(qa, d[1], u[0][t]);
+        u[1][t] = cfma(qa, d[2], cfma(qb, d[0], u[1][t]));
+        u[2][t] = cfma(qb, d[1], u[2][t]);
+    }
+}
 
 template <typename R> struct BatchArgs {
     cx<R> *pool;
@@ -181,19 +204,7 @@ __device__ __forceinline__ void batch_xrow_wave(const BatchInst<R> &I, cx<R> *ps
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int t = 0; t < L; ++t) u[j][t] = v[j][t];
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int jp = 0; jp < 3; ++jp)
-                if (I.qxmask & (1u << (3 * j + jp))) {
-                    const cx<R> q = I.qx[3 * j + jp];
-#pragma unroll
-                    for (int t = 0; t < L; ++t) {
-                        const cx<R> pv = t > 0 ? v[jp][t > 0 ? t - 1 : 0] : vb[jp];
-                        const cx<R> nv = t + 1 < L ? v[jp][t + 1 < L ? t + 1 : 0] : va[jp];
-                        u[j][t] = cfma(q, nv - pv, u[j][t]);
-                    }
-                }
+        if (I.sopat) so_neighbours<R, L>(u, v, vb, va, I.qa, I.qb);
 #pragma unroll
         for (int t = 0; t < L; ++t)
             if (t >= len)
@@ -340,19 +351,7 @@ __device__ __forceinline__ void batch_xrow_pair(const BatchInst<R> &I, cx<R> *ps
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int t = 0; t < L; ++t) u[j][t] = v[j][t];
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int jp = 0; jp < 3; ++jp)
-                if (I.qxmask & (1u << (3 * j + jp))) {
-                    const cx<R> q = I.qx[3 * j + jp];
-#pragma unroll
-                    for (int t = 0; t < L; ++t) {
-                        const cx<R> pv = t > 0 ? v[jp][t > 0 ? t - 1 : 0] : vb[jp];
-                        const cx<R> nv = t + 1 < L ? v[jp][t + 1 < L ? t + 1 : 0] : va[jp];
-                        u[j][t] = cfma(q, nv - pv, u[j][t]);
-                    }
-                }
+        if (I.sopat) so_neighbours<R, L>(u, v, vb, va, I.qa, I.qb);
 #pragma unroll
         for (int t = 0; t < L; ++t)
             if (t >= len)
