@@ -28,19 +28,28 @@ __global__ void __launch_bounds__(64) renorm_finalize_kernel(const double *parti
     }
 }
 
-__global__ void __launch_bounds__(256) obs_finalize_kernel(const double *partials, int nblocks, double *out) {
-    __shared__ double red[256];
+__global__ void __launch_bounds__(1024) obs_finalize_kernel(const double *partials, int nblocks, double *out) {
+    __shared__ double red[OBS_NQ][16];
+    double s[OBS_NQ];
+#pragma unroll
+    for (int q = 0; q < OBS_NQ; ++q) s[q] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 1024)
+#pragma unroll
+        for (int q = 0; q < OBS_NQ; ++q) s[q] += partials[(long long)b * OBS_NQ + q];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
     for (int q = 0; q < OBS_NQ; ++q) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(long long)b * OBS_NQ + q];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w >= 1; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[q] = red[0];
-        __syncthreads();
+        double t = s[q];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) t += __shfl_down(t, d, 64);
+        if (lane == 0) red[q][wave] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < OBS_NQ) {
+        const int q = threadIdx.x;
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += red[q][w];
+        out[q] = t;
     }
 }
 

@@ -283,8 +283,10 @@ static unsigned nz_mask(const cd *m) {
 }
 
 // workgroups of the observables pass (each leaves OBS_NQ partial sums)
-constexpr int OBS_MAX_BLOCKS = 1024;
-static int obs_blocks(long long plane) { return (int)std::min<long long>((plane + 255) / 256, OBS_MAX_BLOCKS); }
+constexpr int OBS_MAX_BLOCKS = 1024;  // workgroups of the observables pass (256-point row segments in turn)
+static int obs_blocks(int nx, int ny) {
+    return (int)std::min<long long>((long long)ny * ((nx + 255) / 256), OBS_MAX_BLOCKS);
+}
 
 // --------------------------------------------------------------- grid ---
 enum { MODE_REAL = 0, MODE_IMAG = 1, MODE_ADJ = 2, NMODES = 3 };
@@ -1137,7 +1139,7 @@ static ObsArgs<R> obs_args(int dim, int nx, int ny, double dx, double dy, const 
 template <typename R> static int observables_launch(ssgp_grid g, const void *psi, double *out_dev) {
     ObsArgs<R> a = obs_args<R>(g->dim, g->nx, g->ny, g->dx, g->dy, g->p, g->obs_omega, psi);
     a.partials = g->obs_partials.as<double>();
-    const int nb = obs_blocks(a.plane);
+    const int nb = obs_blocks(a.nx, a.ny);
     LAUNCH_TRY(launch_obs<R>(lc(*g), a, nb));
     LAUNCH_TRY(launch_obs_finalize(lc(*g), g->obs_partials.as<double>(), nb, out_dev));
     return SSGP_OK;
@@ -1318,7 +1320,7 @@ static int observables_noalloc_t(int dim, int nx, int ny, double dx, double dy, 
     double *buf = nullptr;
     SSGP_TRY(scratch_on_current_device(&buf));
     ObsArgs<R> a = obs_args<R>(dim, nx, ny, dx, dy, p, p.omega, psi);
-    const int nb = obs_blocks(a.plane);
+    const int nb = obs_blocks(a.nx, a.ny);
     if (nb > OBS_MAX_BLOCKS) return fail(SSGP_EINVAL, "observables need %d partial blocks, scratch holds %d", nb, OBS_MAX_BLOCKS);
     a.partials = buf;                                 // [nb][OBS_NQ], every slot written by its block
     double *sums = buf + OBS_NQ * OBS_MAX_BLOCKS;     // the OBS_NQ final sums

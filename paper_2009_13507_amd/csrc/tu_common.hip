@@ -10,7 +10,7 @@ hipError_t launch_renorm_finalize(const Launch &c, const double *partials, int n
 }
 
 hipError_t launch_obs_finalize(const Launch &c, const double *partials, int nblocks, double *out) {
-    obs_finalize_kernel<<<1, 256, 0, c.stream>>>(partials, nblocks, out);
+    obs_finalize_kernel<<<1, 1024, 0, c.stream>>>(partials, nblocks, out);
     return hipGetLastError();
 }
 
