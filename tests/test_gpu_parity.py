@@ -142,6 +142,26 @@ def test_observables_match_oracle(dim, so):
             assert abs(obs[k] - ref[k]) < TOL * abs(ref[k]), k
 
 
+@pytest.mark.parametrize("dim,nx,ny", [(1, 2048, 1), (1, 257, 1), (2, 256, 5), (2, 257, 3), (2, 1, 40),
+                                       (2, 600, 500), (2, 1024, 300)])
+def test_observables_row_segments(dim, nx, ny):
+    """The observables pass walks 256-point row segments, a workgroup per
+    segment in turn: widths that fill segments exactly or leave a ragged
+    one, one-point rows, and more segments than workgroups (600 x 500: 1500;
+    1024 x 300: 1200)."""
+    dx = 0.05 if nx >= 1024 else 0.1
+    so = api.SO_PX_SX
+    p = dict(c0=3.0, c2=-0.4, gamma=0.7, omega=0.3, dt=1e-3, so=so)
+    psi0 = start_state(dim, nx, ny, dx, dx, seed=6) + W.random_state((3, ny, nx) if dim == 2 else (3, nx), nx * ny, 1e-3)
+    _, obs = gpu_run(psi0, dx, dx, False, 0, **p)
+    ref = oracle.observables(ocfg(dim, nx, ny, dx, dx, False, **p), psi0)
+    for k in OBS_KEYS:
+        if abs(ref[k]) < 1e-2:
+            assert abs(obs[k] - ref[k]) < 1e-12, k
+        else:
+            assert abs(obs[k] - ref[k]) < TOL * abs(ref[k]), k
+
+
 # ------------------------------------------------ the measured workloads
 def test_1d_workload_full_length():
     """1D, nx = 512, dt = 5e-4, 20000 imaginary-time steps (the whole run)."""
