@@ -485,16 +485,18 @@ template <int L> __host__ __device__ constexpr int srow(int n) { return n + n / 
 //   u_J(i) = s_J(i) + ys_J(i) + sum_j' q[J][j'] (s_j'(i+1) - s_j'(i-1)),
 // with s the staged row (zero outside [0, nx)) and ys optional precomputed
 // y-derivative terms.  A sliding window reads every staged value once.
+// (pat, qa, qb: the SO coefficient pattern of the x-derivative forms, as
+// XArgs::sopat with 2 for the diagonal one; component J's terms j' = 0, 1, 2)
 template <typename R, int L, int J>
 __device__ __forceinline__ void build_rhs(const cx<R> *s, const cx<R> *ys, int ld, int nx, int start, int len,
-                                          const cx<R> *q, unsigned qmask, cx<R> rdiag,
+                                          int pat, cx<R> qa, cx<R> qb, cx<R> rdiag,
                                           cx<R> (&r)[L]) {
     auto at = [&](int jp, int i) -> cx<R> {
         return (i >= 0 && i < nx) ? s[jp * ld + sidx<L>(i)] : czero<R>();
     };
-    const bool use0 = qmask & (1u << (3 * J + 0)), use1 = qmask & (1u << (3 * J + 1)),
-               use2 = qmask & (1u << (3 * J + 2));
-    const cx<R> q0 = q[3 * J + 0], q1 = q[3 * J + 1], q2 = q[3 * J + 2];
+    const bool use0 = (pat == 1 && J == 1) || (pat == 2 && J == 0), use1 = pat == 1 && J != 1,
+               use2 = (pat == 1 && J == 1) || (pat == 2 && J == 2);
+    const cx<R> q0 = J == 1 ? qb : qa, q1 = J == 0 ? qa : qb, q2 = J == 1 ? qa : qb;
     // window of the coupled components at i-1 and i+1, own component at i
     cx<R> m0{}, m1{}, m2{}, p0{}, p1{}, p2{}, c0{}, c1{}, c2{};
     auto load_win = [&](int i) {
@@ -541,11 +543,11 @@ __device__ __forceinline__ void build_rhs(const cx<R> *s, const cx<R> *ys, int l
 
 template <typename R, int L>
 __device__ __forceinline__ void build_rhs_any(int J, const cx<R> *s, const cx<R> *ys, int ld, int nx, int start,
-                                              int len, const cx<R> *q, unsigned qmask, cx<R> rdiag,
+                                              int len, int pat, cx<R> qa, cx<R> qb, cx<R> rdiag,
                                               cx<R> (&r)[L]) {
-    if (J == 0) build_rhs<R, L, 0>(s, ys, ld, nx, start, len, q, qmask, rdiag, r);
-    else if (J == 1) build_rhs<R, L, 1>(s, ys, ld, nx, start, len, q, qmask, rdiag, r);
-    else build_rhs<R, L, 2>(s, ys, ld, nx, start, len, q, qmask, rdiag, r);
+    if (J == 0) build_rhs<R, L, 0>(s, ys, ld, nx, start, len, pat, qa, qb, rdiag, r);
+    else if (J == 1) build_rhs<R, L, 1>(s, ys, ld, nx, start, len, pat, qa, qb, rdiag, r);
+    else build_rhs<R, L, 2>(s, ys, ld, nx, start, len, pat, qa, qb, rdiag, r);
 }
 
 // ------------------------------------------------------------- x-pass ---
@@ -1527,6 +1529,8 @@ template <typename R> struct Args1D {
     cx<R> rdiag;
     cx<R> qx[9];
     unsigned qxmask;
+    int sopat;                 // what the kernel reads of qx (set by its launcher, so_pattern)
+    cx<R> qa, qb;
     RenormSpec sp;
     int renorm;                // 1: the RENORM rule after every step (imaginary
                                // time; real time when asked for)
@@ -1604,7 +1608,7 @@ __global__ void __launch_bounds__(step1d_threads(L)) step1d_kernel(Args1D<R> a) 
         const int jj = solver ? j : 0;
         cx<R> r[L];
         if (solver)
-            build_rhs_any<R, L>(jj, s, nullptr, ld, nx, start, len, a.qx, a.qxmask, USO ? a.rdiag_u[jj] : a.rdiag,
+            build_rhs_any<R, L>(jj, s, nullptr, ld, nx, start, len, a.sopat, a.qa, a.qb, USO ? a.rdiag_u[jj] : a.rdiag,
                                 r);
         __syncthreads();
         if (solver) solve_line_cached<R, L>(r, len, ccache, Acache, lvcache);
