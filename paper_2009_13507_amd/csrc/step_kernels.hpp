@@ -1559,6 +1559,15 @@ __global__ void __launch_bounds__(step1d_threads(L)) step1d_kernel(Args1D<R> a) 
     cx<R> *s = reinterpret_cast<cx<R> *>(smem_raw);
     __shared__ double red[3];
     __shared__ double dsh[8];
+    // the step loop's scalars, read from LDS after each barrier instead of
+    // being held (and spilled) for the whole run
+    struct Consts {
+        Model<R> m;
+        R x0, dx;
+        cx<R> rdiag, qa, qb;
+    };
+    __shared__ Consts kc;
+    if (threadIdx.x == 0) kc = Consts{a.m, a.x0, a.dx, a.rdiag, a.qa, a.qb};
     const int nx = a.nx;
     const int ld = srow<L>(nx);
     const int tid = threadIdx.x;
@@ -1581,16 +1590,18 @@ __global__ void __launch_bounds__(step1d_threads(L)) step1d_kernel(Args1D<R> a) 
     const cx<R> Acache = lc.chunkA[lane];
     const int lvcache = lc.levels;
     for (int step = 0; step < a.nsteps; ++step) {
+        const Model<R> M = kc.m;
+        const R kx0 = kc.x0, kdx = kc.dx;
         for (int i = tid; i < nx; i += NT) {
             const int si = sidx<L>(i);
             cx<R> p = s[si], z = s[ld + si], m = s[2 * ld + si];
-            const R xv = a.x0 + R(i) * a.dx;
+            const R xv = kx0 + R(i) * kdx;
             if constexpr (P2) {
-                Model<R> Mt = a.m;
-                Mt.dt = R(0.5) * a.m.dt;
+                Model<R> Mt = M;
+                Mt.dt = R(0.5) * M.dt;
                 pointwise2(p, z, m, R(0.5) * xv * xv, Mt);
             } else {
-                pointwise(p, z, m, R(0.5) * xv * xv, a.m);
+                pointwise(p, z, m, R(0.5) * xv * xv, M);
             }
             if constexpr (USO) {
                 cx<R> w[3] = {p, z, m};
@@ -1608,7 +1619,7 @@ __global__ void __launch_bounds__(step1d_threads(L)) step1d_kernel(Args1D<R> a) 
         const int jj = solver ? j : 0;
         cx<R> r[L];
         if (solver)
-            build_rhs_any<R, L>(jj, s, nullptr, ld, nx, start, len, a.sopat, a.qa, a.qb, USO ? a.rdiag_u[jj] : a.rdiag,
+            build_rhs_any<R, L>(jj, s, nullptr, ld, nx, start, len, a.sopat, kc.qa, kc.qb, USO ? a.rdiag_u[jj] : kc.rdiag,
                                 r);
         __syncthreads();
         if (solver) solve_line_cached<R, L>(r, len, ccache, Acache, lvcache);
