@@ -283,8 +283,8 @@ int ssgp_batch_step_imag_serial(ssgp_batch b, int nsteps);
  * k workgroups per compute unit (at most out[2] of ssgp_batch_info), -1 one
  * kernel launch per sweep, 0 re-runs the autotuner at the next step call.
  * -2 and -4 (the grids in 2 or 4 groups of about equal points, one launch
- * per sweep and group, each group on its own stream) are switched off in
- * this build: SSGP_EINVAL, and the autotuner does not time them.
+ * per sweep and group, each group on its own stream) are switched off:
+ * SSGP_EINVAL, and the autotuner does not time them.
  * Synchronises the stream when the shape changes. */
 int ssgp_batch_set_shape(ssgp_batch b, int shape);
 
